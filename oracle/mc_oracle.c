@@ -1,0 +1,312 @@
+/*
+ * mc_oracle.c -- plain, slow, sequential CPU oracle for exact-energy
+ * Metropolis Monte Carlo of the primitive-model electrolyte.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the GPU library; the only thing the two have in
+ * common is the published definition of the Philox4x32-10 generator, which
+ * each side implements on its own.
+ *
+ * Everything is IEEE double (except the explicitly float trial formula of the
+ * FP32 state replay), evaluated in source order; build with
+ * -O2 -ffp-contract=off so that no multiply-add is fused.
+ *
+ * Paper: Liang, Xing, Li, "A GPU-based Large-scale Monte Carlo Simulation
+ * Method for Systems with Long-range Interactions" (arXiv:1602.05716).
+ *   - Sec. 2 "Concurrency": a Monte Carlo step is selection, trial, and
+ *     acceptance with probability min{1, exp(-beta dE)}, Eq. (trial-outcome);
+ *     the sequential updating scheme tries particles 0..N-1 in ascending
+ *     order, each exactly once per cycle (sweep).
+ *   - Sec. 2, Eq. (Delta E_ij): the energy change of step i is the sum over
+ *     j != i of U(x~_i - x_j) - U(x_i - x_j), where x_j is the *current*
+ *     position of j (already updated for j < i).
+ *   - Sec. 3.3 "Energy computation": energy sums are double precision; a
+ *     hard-core overlap is tracked as a separate indicator and rejects the
+ *     trial.
+ *   - Sec. 3.2, Algorithm 1: the trial displacement is (u - 0.5) * D per
+ *     Cartesian component, D being the move range (cube side).
+ *   - Sec. 3.5, Algorithm 4: the trial is accepted when the fourth uniform is
+ *     below exp(-lambda * dE'), lambda the Bjerrum length and dE' the
+ *     Coulomb sum in units of e^2/(4 pi eps); here dE already carries the
+ *     Bjerrum length, so the test reads u3 < exp(-dE) with dE in kT.
+ *   - Sec. 5.2: spherical simulation domain with a hard wall.
+ *
+ * Readings taken where the paper is silent (each is listed in the design
+ * notes): the ion surface may not cross the wall (|x| <= R - sigma/2);
+ * additive hard-sphere diameters, overlap iff r < (sigma_i + sigma_j)/2;
+ * random numbers come from Philox4x32-10 with counter (i, sweep, chain, tag)
+ * and key (seed low word, seed high word) instead of the host-side ran4;
+ * dE <= 0 accepts without evaluating exp().
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, as defined by Salmon, Moraes, Dror and Shaw, "Parallel      */
+/* random numbers: as easy as 1, 2, 3" (SC'11): ten rounds of two 32x32->64   */
+/* multiplications; between rounds the two key words are bumped by the Weyl   */
+/* constants.                                                                  */
+/* ------------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += PHILOX_W0;
+        k1 += PHILOX_W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* The four words of move (ion i, sweep s) of chain c with tag t. */
+static void move_words(uint64_t seed, uint32_t chain, uint32_t sweep, uint32_t i,
+                       uint32_t tag, uint32_t w[4])
+{
+    uint32_t ctr[4] = {i, sweep, chain, tag};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox(ctr, key, w);
+}
+
+void orc_move_words(uint64_t seed, uint32_t chain, uint32_t sweep, uint32_t i,
+                    uint32_t tag, uint32_t w[4])
+{
+    move_words(seed, chain, sweep, i, tag, w);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair energy and the energy change of one trial move.                       */
+/* ------------------------------------------------------------------------ */
+
+/* Squared distance, summed left to right with no fused multiply-add. */
+static double dist2(const double* a, const double* b)
+{
+    double dx = a[0] - b[0];
+    double dy = a[1] - b[1];
+    double dz = a[2] - b[2];
+    return dx * dx + dy * dy + dz * dz;
+}
+
+/*
+ * Total Coulomb energy in kT: E = l_B * sum_{i<j} q_i q_j / r_ij (Sec. 5.1,
+ * the bare pair potential; beta e^2 / (4 pi eps) = l_B).  No self term, no
+ * wall energy, no image charges.  Order: i ascending, j ascending.
+ */
+double orc_total_energy(int32_t n, const double* xyz, const double* q, double lB)
+{
+    double e = 0.0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = i + 1; j < n; ++j)
+            e += q[i] * q[j] / sqrt(dist2(xyz + 3 * i, xyz + 3 * j));
+    return lB * e;
+}
+
+/*
+ * Energy change of moving ion i from xyz[i] to xt (Eq. Delta E_ij summed
+ * over j != i, with the positions currently held in xyz), in kT, plus the
+ * hard-core overlap indicator of Sec. 3.3 evaluated at the trial position.
+ * The sum runs over j in ascending order and is never cut short: the
+ * indicator is carried alongside the sum, as in the GPU scheme of Sec. 3.3.
+ */
+double orc_delta_energy(int32_t n, const double* xyz, const double* q,
+                        const double* sigma, int32_t i, const double* xt,
+                        double lB, int32_t* overlap)
+{
+    const double* xi = xyz + 3 * i;
+    double s = 0.0;
+    int ov = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const double* xj = xyz + 3 * j;
+        double d2t = dist2(xt, xj);
+        double d2 = dist2(xi, xj);
+        double sij = 0.5 * (sigma[i] + sigma[j]);
+        if (d2t < sij * sij) ov = 1;
+        s += q[j] * (1.0 / sqrt(d2t) - 1.0 / sqrt(d2));
+    }
+    if (overlap) *overlap = ov;
+    return lB * q[i] * s;
+}
+
+/* Hard wall (Sec. 5.2, reading: the ion surface stays inside radius R). */
+static int outside_wall(const double* x, double R, double sigma)
+{
+    double a = R - 0.5 * sigma;
+    double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    return r2 > a * a;
+}
+
+int32_t orc_outside_wall(const double* x, double R, double sigma)
+{
+    return outside_wall(x, R, sigma);
+}
+
+/* Metropolis test, Eq. (trial-outcome) with Algorithm 4's uniform. */
+static int metropolis(double dE, double u3)
+{
+    return dE <= 0.0 || u3 < exp(-dE);
+}
+
+/* Trial position in double: x~ = x + D (u - 1/2), u = w 2^-32 (Algorithm 1). */
+static void trial_f64(const double* x, const uint32_t w[4], double D, double* xt)
+{
+    for (int k = 0; k < 3; ++k) {
+        double u = (double)w[k] * 0x1p-32;
+        double t = u - 0.5;
+        t = D * t;
+        xt[k] = x[k] + t;
+    }
+}
+
+void orc_trial_f64(const double* x, const uint32_t w[4], double D, double* xt)
+{
+    trial_f64(x, w, D, xt);
+}
+
+/*
+ * n_sweeps sequential sweeps starting at sweep index sweep0 (Sec. 2,
+ * sequential updating scheme).  xyz and *e_run are updated in place.  For the
+ * first out_cap moves the accept bit and dE are written to acc_out/de_out
+ * (either may be NULL); flags_out (nullable) receives bit0 = wall,
+ * bit1 = overlap for those moves.  e_series (nullable) receives the running
+ * energy after each sweep.  Returns the number of accepted moves.
+ */
+int64_t orc_sweeps_f64(int32_t n, double* xyz, const double* q, const double* sigma,
+                       double R, double lB, double D, uint64_t seed, uint32_t chain,
+                       uint32_t sweep0, int32_t n_sweeps, double* e_run,
+                       uint8_t* acc_out, double* de_out, uint8_t* flags_out,
+                       int64_t out_cap, double* e_series)
+{
+    int64_t accepted = 0, m = 0;
+    for (int32_t s = 0; s < n_sweeps; ++s) {
+        uint32_t sweep = sweep0 + (uint32_t)s;
+        for (int32_t i = 0; i < n; ++i, ++m) {
+            uint32_t w[4];
+            move_words(seed, chain, sweep, (uint32_t)i, 0u, w);
+            double xt[3];
+            trial_f64(xyz + 3 * i, w, D, xt);
+            int wall = outside_wall(xt, R, sigma[i]);
+            int ov = 0;
+            double dE = orc_delta_energy(n, xyz, q, sigma, i, xt, lB, &ov);
+            double u3 = (double)w[3] * 0x1p-32;
+            int acc = !wall && !ov && metropolis(dE, u3);
+            if (acc) {
+                xyz[3 * i + 0] = xt[0];
+                xyz[3 * i + 1] = xt[1];
+                xyz[3 * i + 2] = xt[2];
+                *e_run += dE;
+                ++accepted;
+            }
+            if (m < out_cap) {
+                if (acc_out) acc_out[m] = (uint8_t)acc;
+                if (de_out) de_out[m] = dE;
+                if (flags_out) flags_out[m] = (uint8_t)(wall | (ov << 1));
+            }
+        }
+        if (e_series) e_series[s] = *e_run;
+    }
+    return accepted;
+}
+
+/*
+ * FP32-state replay.  The state is a float array (the paper keeps positions
+ * in float4, Sec. 3.1) and the trial position is formed in float:
+ * u = (w >> 8) 2^-24, t = u - 1/2, t = D t, x~ = x + t, each step rounded to
+ * float.  The trajectory follows the decisions in acc_given (one byte per
+ * move, e.g. produced by another implementation), so that every move is
+ * evaluated on exactly the state that implementation saw.  For each move the
+ * exact double dE over that float state, the wall/overlap flags, the accept
+ * uniform u3 = w3 2^-32 and this oracle's own decision are returned.
+ * Returns the number of moves where acc_given differs from the oracle's own
+ * decision.
+ */
+int64_t orc_replay_f32(int32_t n, float* xyz, const double* q, const double* sigma,
+                       double R, double lB, float D, uint64_t seed, uint32_t chain,
+                       uint32_t sweep0, int64_t n_moves, const uint8_t* acc_given,
+                       double* de_out, double* u3_out, uint8_t* flags_out,
+                       uint8_t* own_out)
+{
+    double* xd = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!xd) return -1;
+    for (int64_t k = 0; k < 3 * (int64_t)n; ++k) xd[k] = (double)xyz[k];
+    int64_t mismatches = 0;
+    for (int64_t m = 0; m < n_moves; ++m) {
+        int32_t i = (int32_t)(m % n);
+        uint32_t sweep = sweep0 + (uint32_t)(m / n);
+        uint32_t w[4];
+        move_words(seed, chain, sweep, (uint32_t)i, 0u, w);
+        float xtf[3];
+        for (int k = 0; k < 3; ++k) {
+            float u = (float)(w[k] >> 8) * 0x1p-24f;
+            float t = u - 0.5f;
+            t = D * t;
+            xtf[k] = xyz[3 * i + k] + t;
+        }
+        double xt[3] = {(double)xtf[0], (double)xtf[1], (double)xtf[2]};
+        int wall = outside_wall(xt, R, sigma[i]);
+        int ov = 0;
+        double dE = orc_delta_energy(n, xd, q, sigma, i, xt, lB, &ov);
+        double u3 = (double)w[3] * 0x1p-32;
+        int own = !wall && !ov && metropolis(dE, u3);
+        int acc = acc_given ? (int)acc_given[m] : own;
+        if (acc != own) ++mismatches;
+        if (de_out) de_out[m] = dE;
+        if (u3_out) u3_out[m] = u3;
+        if (flags_out) flags_out[m] = (uint8_t)(wall | (ov << 1));
+        if (own_out) own_out[m] = (uint8_t)own;
+        if (acc) {
+            for (int k = 0; k < 3; ++k) {
+                xyz[3 * i + k] = xtf[k];
+                xd[3 * i + k] = xt[k];
+            }
+        }
+    }
+    free(xd);
+    return mismatches;
+}
+
+/*
+ * Radial distribution counts (Sec. 5.2): centres are the ions whose centre
+ * lies within R - r_max of the origin (so that every shell up to r_max is
+ * inside the domain -- the reading of "ions near the boundary are not used
+ * for data collection"); neighbours are all other ions.  Ordered pairs.
+ * Bin k = floor(r / dr), dr = r_max / bins, pairs with r >= r_max dropped.
+ * counts[(ti * ntypes + tj) * bins + k] and centres[ti] are incremented.
+ */
+void orc_rdf_counts(int32_t n, const double* xyz, const int32_t* type, int32_t ntypes,
+                    double R, double rmax, int32_t bins, uint64_t* counts,
+                    uint64_t* centres)
+{
+    double dr = rmax / (double)bins;
+    double rc = R - rmax;
+    for (int32_t i = 0; i < n; ++i) {
+        const double* xi = xyz + 3 * i;
+        double r2i = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+        if (rc < 0.0 || r2i > rc * rc) continue;
+        centres[type[i]] += 1;
+        for (int32_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r = sqrt(dist2(xi, xyz + 3 * j));
+            if (r >= rmax) continue;
+            int32_t k = (int32_t)floor(r / dr);
+            if (k >= bins) continue;
+            counts[((int64_t)type[i] * ntypes + type[j]) * bins + k] += 1;
+        }
+    }
+}

@@ -1,0 +1,287 @@
+"""ctypes front end of the C oracle plus the oracle's host-side analysis.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the library.  The GPU path shares
+no code with it.
+
+Paper: Liang, Xing, Li, arXiv:1602.05716.  The C part (mc_oracle.c) holds the
+Markov chain itself; this module adds
+  * g_ab(r) normalisation of the integer pair counts (Sec. 5.2, pair
+    correlation functions),
+  * the integrated autocorrelation time T_c = 1/2 + sum_k C_k of the energy
+    series (Sec. 5.2, definitions of C_n and T_c), truncated with Sokal's
+    automatic window (the paper does not say where to stop the sum),
+  * Debye-Hueckel closed forms (Sec. 5.1, Eq. (alpha-kappa_0) and the PB pair
+    potential) used by the dilute-limit test.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mc_oracle.c")
+_LIB = os.path.join(_HERE, "libmc_oracle.so")
+
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_f32p = ctypes.POINTER(ctypes.c_float)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no fused multiply-add)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                               "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        L.orc_philox.argtypes = [_u32p, _u32p, _u32p]
+        L.orc_philox.restype = None
+        L.orc_move_words.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_uint32, ctypes.c_uint32, _u32p]
+        L.orc_move_words.restype = None
+        L.orc_total_energy.argtypes = [ctypes.c_int32, _f64p, _f64p, ctypes.c_double]
+        L.orc_total_energy.restype = ctypes.c_double
+        L.orc_delta_energy.argtypes = [ctypes.c_int32, _f64p, _f64p, _f64p, ctypes.c_int32,
+                                       _f64p, ctypes.c_double, _i32p]
+        L.orc_delta_energy.restype = ctypes.c_double
+        L.orc_outside_wall.argtypes = [_f64p, ctypes.c_double, ctypes.c_double]
+        L.orc_outside_wall.restype = ctypes.c_int32
+        L.orc_trial_f64.argtypes = [_f64p, _u32p, ctypes.c_double, _f64p]
+        L.orc_trial_f64.restype = None
+        L.orc_sweeps_f64.argtypes = [ctypes.c_int32, _f64p, _f64p, _f64p, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int32, _f64p,
+                                     _u8p, _f64p, _u8p, ctypes.c_int64, _f64p]
+        L.orc_sweeps_f64.restype = ctypes.c_int64
+        L.orc_replay_f32.argtypes = [ctypes.c_int32, _f32p, _f64p, _f64p, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_float, ctypes.c_uint64,
+                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64, _u8p,
+                                     _f64p, _f64p, _u8p, _u8p]
+        L.orc_replay_f32.restype = ctypes.c_int64
+        L.orc_rdf_counts.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int32,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int32, _u64p,
+                                     _u64p]
+        L.orc_rdf_counts.restype = None
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+# --------------------------------------------------------------------------- #
+# Random numbers                                                              #
+# --------------------------------------------------------------------------- #
+
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 block function (Salmon et al., SC'11)."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox(_p(c, _u32p), _p(k, _u32p), _p(out, _u32p))
+    return out
+
+
+def move_words(seed: int, chain: int, sweep: int, i: int, tag: int = 0) -> np.ndarray:
+    """The four Philox words of trial move (ion i, sweep) of a chain."""
+    out = np.zeros(4, np.uint32)
+    lib().orc_move_words(seed, chain, sweep, i, tag, _p(out, _u32p))
+    return out
+
+
+# --------------------------------------------------------------------------- #
+# Energies and the chain                                                      #
+# --------------------------------------------------------------------------- #
+
+def total_energy(xyz, q, lB) -> float:
+    """E = l_B sum_{i<j} q_i q_j / r_ij in kT (bare Coulomb, Sec. 5.1)."""
+    x = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)
+    qq = np.ascontiguousarray(q, np.float64)
+    return lib().orc_total_energy(len(qq), _p(x, _f64p), _p(qq, _f64p), lB)
+
+
+def delta_energy(xyz, q, sigma, i, xt, lB):
+    """(dE, overlap) for moving ion i to xt; Eq. (Delta E_ij) summed over j."""
+    x = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)
+    qq = np.ascontiguousarray(q, np.float64)
+    ss = np.ascontiguousarray(sigma, np.float64)
+    t = np.ascontiguousarray(xt, np.float64)
+    ov = ctypes.c_int32(0)
+    dE = lib().orc_delta_energy(len(qq), _p(x, _f64p), _p(qq, _f64p), _p(ss, _f64p), int(i),
+                                _p(t, _f64p), lB, ctypes.byref(ov))
+    return dE, bool(ov.value)
+
+
+class Chain:
+    """Sequential-update Metropolis chain in double precision (Sec. 2).
+
+    ``run(n)`` performs n sweeps; each sweep tries ions 0..N-1 once, in order.
+    """
+
+    def __init__(self, xyz, q, sigma, R, lB, D, seed, chain=0, sweep=0):
+        self.x = np.array(xyz, np.float64).reshape(-1, 3).copy()
+        self.q = np.ascontiguousarray(q, np.float64)
+        self.sigma = np.ascontiguousarray(sigma, np.float64)
+        self.n = len(self.q)
+        self.R, self.lB, self.D = float(R), float(lB), float(D)
+        self.seed, self.chain, self.sweep = int(seed), int(chain), int(sweep)
+        self.e_run = total_energy(self.x, self.q, self.lB)
+        self.accepted = 0
+
+    def run(self, n_sweeps, trace=0, series=False):
+        cap = int(trace)
+        acc = np.zeros(max(cap, 1), np.uint8)
+        de = np.zeros(max(cap, 1), np.float64)
+        fl = np.zeros(max(cap, 1), np.uint8)
+        es = np.zeros(max(n_sweeps, 1), np.float64) if series else None
+        e = ctypes.c_double(self.e_run)
+        nacc = lib().orc_sweeps_f64(self.n, _p(self.x, _f64p), _p(self.q, _f64p),
+                                    _p(self.sigma, _f64p), self.R, self.lB, self.D,
+                                    self.seed, self.chain, self.sweep, int(n_sweeps),
+                                    ctypes.byref(e), _p(acc, _u8p), _p(de, _f64p),
+                                    _p(fl, _u8p), cap, _p(es, _f64p))
+        self.e_run = e.value
+        self.sweep += int(n_sweeps)
+        self.accepted += int(nacc)
+        out = {"accepted": int(nacc)}
+        if cap:
+            out.update(acc=acc[:cap], dE=de[:cap], flags=fl[:cap])
+        if series:
+            out["e_series"] = es[:n_sweeps]
+        return out
+
+
+def replay_f32(xyz_f32, q, sigma, R, lB, D, seed, chain, sweep0, n_moves, acc_given=None):
+    """Exact double dE of each move along a float-state trajectory.
+
+    The trajectory follows ``acc_given`` (e.g. another implementation's
+    decisions); returns dict with dE, u3, flags (bit0 wall, bit1 overlap),
+    the oracle's own decision per move, the final float state and the number
+    of moves whose given decision differs from the oracle's.
+    """
+    x = np.array(xyz_f32, np.float32).reshape(-1, 3).copy()
+    qq = np.ascontiguousarray(q, np.float64)
+    ss = np.ascontiguousarray(sigma, np.float64)
+    n = len(qq)
+    de = np.zeros(n_moves, np.float64)
+    u3 = np.zeros(n_moves, np.float64)
+    fl = np.zeros(n_moves, np.uint8)
+    own = np.zeros(n_moves, np.uint8)
+    ag = None if acc_given is None else np.ascontiguousarray(acc_given, np.uint8)
+    mism = lib().orc_replay_f32(n, _p(x, _f32p), _p(qq, _f64p), _p(ss, _f64p), R, lB,
+                                np.float32(D), seed, chain, sweep0, int(n_moves),
+                                _p(ag, _u8p), _p(de, _f64p), _p(u3, _f64p), _p(fl, _u8p),
+                                _p(own, _u8p))
+    return {"dE": de, "u3": u3, "flags": fl, "own": own, "xyz": x, "mismatches": int(mism)}
+
+
+# --------------------------------------------------------------------------- #
+# Pair correlation functions                                                  #
+# --------------------------------------------------------------------------- #
+
+def rdf_counts(xyz, types, ntypes, R, rmax, bins):
+    """Integer pair counts C[a, b, k] and centre counts (Sec. 5.2 estimator)."""
+    x = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)
+    t = np.ascontiguousarray(types, np.int32)
+    counts = np.zeros((ntypes, ntypes, bins), np.uint64)
+    centres = np.zeros(ntypes, np.uint64)
+    lib().orc_rdf_counts(len(t), _p(x, _f64p), _p(t, _i32p), ntypes, R, rmax, bins,
+                         _p(counts, _u64p), _p(centres, _u64p))
+    return counts, centres
+
+
+def rdf_normalise(counts, centres, n_of_type, sigma_of_type, R, rmax, bins, n_samples=1):
+    """g_ab(r_k) = C_ab(k) / (Ncentre_a n_b V_k).
+
+    n_b = (N_b - delta_ab) / ((4/3) pi (R - sigma_b/2)^3) is the density of
+    possible neighbours of type b in the region their centres can reach and
+    V_k the shell volume.  Centre counts and pair counts are totals over
+    ``n_samples`` samples (the centre counts already include every sample).
+    """
+    counts = np.asarray(counts, np.float64)
+    centres = np.asarray(centres, np.float64)
+    nt = counts.shape[0]
+    dr = rmax / bins
+    edges = np.arange(bins + 1) * dr
+    vk = 4.0 / 3.0 * np.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    g = np.zeros_like(counts)
+    for a in range(nt):
+        for b in range(nt):
+            vb = 4.0 / 3.0 * np.pi * (R - 0.5 * sigma_of_type[b]) ** 3
+            nb = (n_of_type[b] - (1 if a == b else 0)) / vb
+            if centres[a] > 0:
+                g[a, b] = counts[a, b] / (centres[a] * nb * vk)
+    return g, 0.5 * (edges[1:] + edges[:-1])
+
+
+# --------------------------------------------------------------------------- #
+# Autocorrelation / effective sample size                                     #
+# --------------------------------------------------------------------------- #
+
+def autocorr(series, max_lag=None):
+    """C_n of Sec. 5.2: normalised autocovariance of the series at lag n."""
+    e = np.asarray(series, np.float64)
+    e = e - e.mean()
+    n = len(e)
+    max_lag = n - 1 if max_lag is None else min(max_lag, n - 1)
+    var = np.dot(e, e) / n
+    if var == 0.0:
+        return np.zeros(max_lag + 1)
+    c = np.array([np.dot(e[: n - k], e[k:]) / n for k in range(max_lag + 1)])
+    return c / var
+
+
+def tau_int(series, c_window=5.0):
+    """T_c = 1/2 + sum_{k>=1} C_k, the sum stopped at the first M >= c T_c(M)."""
+    c = autocorr(series)
+    tau = 0.5
+    for m in range(1, len(c)):
+        tau += c[m]
+        if m >= c_window * tau:
+            return tau
+    return tau
+
+
+def ess(series, c_window=5.0):
+    """Effective sample size n / (2 T_c)."""
+    return len(series) / (2.0 * tau_int(series, c_window))
+
+
+# --------------------------------------------------------------------------- #
+# Debye-Hueckel closed forms (Sec. 5.1)                                       #
+# --------------------------------------------------------------------------- #
+
+def debye_kappa(lB, densities, charges):
+    """kappa^2 = 4 pi l_B sum_a n_a q_a^2 (Eq. (alpha-kappa_0) with beta e^2/eps = 4 pi l_B)."""
+    return float(np.sqrt(4.0 * np.pi * lB * np.sum(np.asarray(densities) * np.asarray(charges) ** 2)))
+
+
+def dh_log_ratio(r, lB, kappa, sigma):
+    """ln(g_{+-}/g_{++}) for a symmetric 1:1 electrolyte in the linearised DH limit.
+
+    The PB pair potential of mean force beta U = q1 q2 l_B exp(-kappa r)/r
+    (Sec. 5.1) with the finite-size (extended DH) factor
+    exp(kappa sigma)/(1 + kappa sigma); -ln g = beta U gives the ratio
+    2 l_B exp(-kappa (r - sigma)) / (r (1 + kappa sigma)).
+    """
+    r = np.asarray(r, np.float64)
+    return 2.0 * lB * np.exp(-kappa * (r - sigma)) / (r * (1.0 + kappa * sigma))
