@@ -1,0 +1,189 @@
+"""Benchmark: exact-energy sequential Metropolis MC of the 1:1 primitive model
+at N = 32768 on one MI355X.
+
+One step = mc_sweep of --sweeps-per-step sweeps (default 100) of the whole
+hot path: the persistent sweep kernel (trial draw, exact dE over all N-1
+partners with the hard-core test, sequential accept/reject, in-place update)
+followed by the double-precision energy re-sum that closes the interval.
+
+Workload: 16384 cations (+1) and 16384 anions (-1), sigma = 1, l_B = 0.7,
+hard-wall sphere at volume fraction 0.05, seeded random start (synthetic),
+float positions and pair terms with double per-move and running-energy sums;
+the trial cube is tuned to about 40 % acceptance during warm-up and then
+frozen.  Prints one JSON line (see the repository's design notes for the
+roofline and CPU-baseline definitions).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MC moves/s + pair terms/s at N=32768; ESS/s plain vs batched vs surrogate-DA"
+CUS, CLOCK_HZ = 256, 2.4e9
+# v_rsq_f32 issue rate per CU per clock on gfx950 (lanes); the VALU probe
+# (valu_peak) measures it on the device and bench reports both.
+RSQ_LANES_PER_CLK_CU = 16.0
+RSQ_PER_PAIR = 2
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def tune_max_disp(chain, max_disp, target=0.40, rounds=8, sweeps=4, seed=0xD15C):
+    """Warm-up only: D <- D * clamp(acc / target, 1/2, 2) after each round."""
+    md = max_disp
+    for r in range(rounds):
+        chain.set_max_disp(md)
+        st0 = chain.stats()
+        chain.sweep(sweeps, seed + r)
+        st1 = chain.stats()
+        acc = (st1["accepted"] - st0["accepted"]) / max(1, st1["moves"] - st0["moves"])
+        log("tune round %d: max_disp %.4f acceptance %.4f" % (r, md, acc))
+        md *= min(2.0, max(0.5, acc / target))
+    chain.set_max_disp(md)
+    return md
+
+
+def cpu_baseline(system, D, seed, sweeps=1):
+    """The FP64 oracle, serial, on the same system and start (bounded sample)."""
+    from oracle import oracle
+    ch = oracle.Chain(system.xyz, system.q, system.sigma, system.R, system.lB, D, seed=seed)
+    t0 = time.perf_counter()
+    ch.run(sweeps)
+    dt = time.perf_counter() - t0
+    n = system.n
+    return {"value": sweeps * n / dt, "unit": "moves/s", "cores": 1, "kind": "oracle",
+            "pair_terms_per_s": sweeps * n * (n - 1) / dt,
+            "sample": "%d sweep(s) = %d moves of the same N=%d system and start, FP64 oracle, "
+                      "1 thread, %.1f s" % (sweeps, sweeps * n, n, dt)}
+
+
+def run_valu_probe():
+    exe = os.path.join(ROOT, "paper_1602_05716_amd", "valu_peak")
+    if not os.path.exists(exe):
+        return None
+    try:
+        out = subprocess.run([exe], capture_output=True, text=True, timeout=60, check=True).stdout
+        return json.loads(out.strip().splitlines()[-1])
+    except Exception as e:  # the probe is informational
+        log("valu probe failed:", e)
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sweeps-per-step", type=int, default=100)
+    ap.add_argument("--seed", type=int, default=0x5EED0002)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sweeps", type=int, default=1)
+    ap.add_argument("--no-probe", action="store_true", help="skip the VALU issue-rate probe")
+    ap.add_argument("--band", type=int, default=-1)
+    ap.add_argument("--waves", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: a single chain does not shard across GPUs "
+              "(independent chains would, see the design notes); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1602_05716_amd import analysis, inputs, mc
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.init()
+    stream = torch.cuda.Stream()  # default priority; the chain enqueues all its work here
+
+    log("building the N=32768 start")
+    system = inputs.large_fp32()
+    n = system.n
+    chain = mc.Chain(system.xyz, system.q, system.sigma, system.R, system.lB, precision="fp32",
+                     max_disp=0.5, resum_every=args.sweeps_per_step, record_timing=1,
+                     hip_stream=stream.cuda_stream, band=args.band, waves=args.waves)
+    md = tune_max_disp(chain, 0.5)
+    log("frozen max_disp %.4f" % md)
+    for _ in range(args.warmup):
+        chain.sweep(args.sweeps_per_step, args.seed)
+    chain.energy()
+    st0 = chain.stats()
+    chain.timing_reset()
+    sweeps0 = st0["sweeps"]
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        chain.sweep(args.sweeps_per_step, args.seed)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+
+    st1 = chain.stats()
+    launches, kernel_ms, kernel_sweeps = chain.timing()
+    series = chain.energy_series(st1["sweeps"])[sweeps0:]
+    e_run, e_exact = chain.energy(exact=True)
+    sweeps = args.steps * args.sweeps_per_step
+    moves = sweeps * n
+    pairs = sweeps * n * (n - 1)
+    acc = (st1["accepted"] - st0["accepted"]) / max(1, st1["moves"] - st0["moves"])
+    ess = analysis.effective_samples(series) if len(series) > 8 else float("nan")
+    tau = analysis.integrated_time(series) if len(series) > 8 else float("nan")
+
+    # dominant kernel: the persistent sweep kernel, timed by HIP events on its stream
+    avg_launch_s = kernel_ms * 1e-3 / max(1, launches)
+    per_launch_rsq = (kernel_sweeps / max(1, launches)) * n * (n - 1) * RSQ_PER_PAIR
+    achieved = per_launch_rsq / avg_launch_s / 1e12
+    peak = CUS * CLOCK_HZ * RSQ_LANES_PER_CLK_CU / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Trsqrt/s",
+                "frac": achieved / peak, "traffic": None,
+                "kernel": "sweep_kernel<float,%d>" % st1["waves"],
+                "avg_launch_ms": avg_launch_s * 1e3, "launches": launches,
+                "sweeps_per_launch": kernel_sweeps / max(1, launches)}
+    probe = None if args.no_probe else run_valu_probe()
+    if probe:
+        roofline["probe"] = probe
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle (%d sweep(s))" % args.cpu_sweeps)
+        cpu = cpu_baseline(system, 2.0 * md, args.seed, args.cpu_sweeps)
+        cpu["cores_available"] = os.cpu_count()
+        cpu["gpu_over_cpu"] = (moves / elapsed) / cpu["value"]
+
+    out = {
+        "metric": METRIC, "value": moves / elapsed, "unit": "moves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1:1 primitive model, N=32768 (16384 +1 / 16384 -1), sigma=1, "
+                               "l_B=0.7, hard-wall sphere phi=0.05, seeded random start",
+                   "n_ions": n, "sweeps_per_step": args.sweeps_per_step,
+                   "precision": "f32 pair terms, f64 per-move and running sums",
+                   "max_disp": md, "acceptance": acc, "band": st1["band"], "waves": st1["waves"],
+                   "workgroups": st1["workgroups"]},
+        "pair_terms_per_s": pairs / elapsed,
+        "ess_per_s": {"plain": ess / elapsed, "batched": None, "surrogate_da": None},
+        "energy": {"tau_int_sweeps": tau, "e_running": e_run, "e_resum": e_exact,
+                   "max_abs_drift_per_resum": st1["max_abs_drift"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "context": "paper: 440x over a serial CPU code on a Tesla K20 (quoted, not a target)",
+    }
+    chain.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+/*
+ * mc.h -- C ABI of the MI355X (gfx950) exact-energy Metropolis Monte Carlo
+ * library for primitive-model electrolytes.
+ *
+ * Method: Liang, Xing, Li, "A GPU-based Large-scale Monte Carlo Simulation
+ * Method for Systems with Long-range Interactions" (arXiv:1602.05716).
+ *   - Sec. 2: canonical Metropolis Monte Carlo with the sequential updating
+ *     scheme -- one sweep (cycle) tries ions 0..N-1 once each, in order; a
+ *     trial is accepted with probability min{1, exp(-beta dE)}, Eq.
+ *     (trial-outcome).
+ *   - Sec. 2, Eq. (Delta E_ij): dE of trial i is the exact sum over all other
+ *     ions of the pair-energy change, using the current position of every
+ *     other ion (already updated for j < i).  No cutoff, multipole or Ewald
+ *     approximation.
+ *   - Sec. 3.3: energies are accumulated in double precision; a hard-core
+ *     overlap indicator rejects the trial.
+ *   - Sec. 3.2, Algorithm 1: the trial displacement is uniform in a cube of
+ *     side D centred on the ion.
+ *   - Sec. 5.2: spherical hard-wall domain; total energy is monitored during
+ *     equilibration; pair correlation functions g_ab(r) are measured on ions
+ *     away from the wall.
+ *
+ * Model (readings of the paper, see the design notes): charged hard spheres
+ * of diameter sigma_i and valence q_i in a continuum of Bjerrum length l_B,
+ * pair energy U_ij/kT = l_B q_i q_j / r_ij; overlap iff
+ * r_ij < (sigma_i + sigma_j)/2; the ion surface may not cross the wall,
+ * |x_i| <= R - sigma_i/2.  Lengths are in the caller's unit, energies in kT.
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11), one block per trial,
+ * counter (i, sweep, chain_id, 0), key (seed low word, seed high word);
+ * words 0..2 give the displacement, word 3 the accept uniform.
+ *
+ * Conventions for every call:
+ *   - All pointer arguments are HOST pointers unless stated otherwise; the
+ *     library copies what it needs and never keeps a caller pointer.
+ *   - Every function returns MC_OK (0) or a negative mc_status; no exception
+ *     or longjmp crosses this interface.  mc_last_error() describes the last
+ *     failure of a handle.
+ *   - A handle is not thread safe; calls on one handle must be serialised.
+ *   - Work is enqueued on the handle's HIP stream; getters that return data
+ *     synchronise that stream first.
+ */
+#ifndef MC_H_
+#define MC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mc_handle mc_handle;
+
+typedef enum mc_status {
+    MC_OK = 0,
+    MC_E_ARG = -1,          /* bad argument (null, size, non-finite, range)       */
+    MC_E_OVERLAP = -2,      /* input positions have a hard-core overlap           */
+    MC_E_WALL = -3,         /* an input ion crosses the wall                      */
+    MC_E_NOT_NEUTRAL = -4,  /* sum of charges is not zero                         */
+    MC_E_DEVICE = -5,       /* HIP runtime error, or the HIP device is missing    */
+    MC_E_OOM = -6,          /* device memory allocation failed                    */
+    MC_E_TIMEOUT = -7,      /* a device-side wait exceeded its time limit         */
+    MC_E_STATE = -8         /* handle in a bad state (e.g. after a device error)  */
+} mc_status;
+
+typedef enum mc_precision {
+    MC_FP64 = 0,            /* positions and pair terms in double                 */
+    MC_FP32_ACC64 = 1       /* positions and pair terms in float; per-move dE and
+                               the running energy accumulated in double           */
+} mc_precision;
+
+/*
+ * Options; call mc_options_init() first, then change fields.  Passing NULL
+ * wherever an mc_options* is accepted means the defaults.
+ */
+typedef struct mc_options {
+    int32_t precision;      /* mc_precision, default MC_FP32_ACC64                */
+    double max_disp;        /* half side of the trial cube, D = 2 * max_disp
+                               (Algorithm 1's "range of one moving" is D);
+                               default 0.5                                         */
+    int32_t resum_every;    /* re-sum the total energy in double every this many
+                               sweeps inside mc_sweep and reset the running
+                               energy to it (0 = never); default 100               */
+    int32_t rdf_every;      /* accumulate g(r) counts every this many sweeps
+                               inside mc_sweep (0 = never); default 0              */
+    int32_t rdf_bins;       /* histogram bins, default 200                         */
+    double rdf_rmax;        /* histogram range, default 10                         */
+    uint32_t chain_id;      /* Philox counter word 2, default 0                    */
+    void* hip_stream;       /* hipStream_t to enqueue on (e.g. a PyTorch stream);
+                               NULL = a stream owned by the handle                 */
+    int32_t band;           /* look-ahead band width in 64-ion groups (0..4),
+                               -1 = automatic; affects speed only                  */
+    int32_t waves;          /* waves per workgroup (4 or 8), 0 = automatic         */
+    int32_t workgroups;     /* workgroups serving the chain, 0 = automatic         */
+    int64_t trace_moves;    /* record accept bit and dE of the first this many
+                               moves of the chain (global move index
+                               sweep * N + i), 0 = off                             */
+    double wait_timeout_s;  /* limit of any single device-side wait, default 20   */
+    int32_t record_timing;  /* nonzero: time every sweep-kernel launch with HIP
+                               events on the handle's stream (see mc_timing)     */
+} mc_options;
+
+/* Fills *opt with the defaults.  Returns MC_E_ARG if opt is NULL. */
+int mc_options_init(mc_options* opt);
+
+/*
+ * Creates a chain.
+ *   n          number of ions, 1 <= n <= 2^24.
+ *   charges    [n] valences q_i (finite); their sum must be 0 within 1e-9 * sum|q|.
+ *   diameters  [n] hard-sphere diameters sigma_i > 0.
+ *   positions  [n*3] x,y,z per ion (row-major); must lie inside the wall and
+ *              be free of overlaps (r_ij >= (sigma_i + sigma_j)/2).
+ *   radius     wall radius R > 0.
+ *   l_B        Bjerrum length >= 0 (pair energy l_B q_i q_j / r in kT).
+ *   opt        options or NULL.
+ *   out        receives the handle.
+ * The initial total energy is computed on the device in double.  Errors:
+ * MC_E_ARG, MC_E_NOT_NEUTRAL, MC_E_WALL, MC_E_OVERLAP, MC_E_DEVICE, MC_E_OOM.
+ * On error *out is set to NULL and nothing is leaked.
+ */
+int mc_create(int32_t n, const double* charges, const double* diameters,
+              const double* positions, double radius, double l_B,
+              const mc_options* opt, mc_handle** out);
+
+/*
+ * Enqueues n_sweeps >= 0 sequential sweeps (Sec. 2) continuing the handle's
+ * sweep counter; the random stream is keyed by seed, so a chain continued
+ * with the same seed is identical to one run in a single call.  The energy
+ * re-sum and g(r) sampling of the options are interleaved at sweep counts
+ * that are multiples of their intervals.  Asynchronous: returns once the work
+ * is enqueued; device errors surface on the next synchronising call.
+ */
+int mc_sweep(mc_handle* h, int64_t n_sweeps, uint64_t seed);
+
+/*
+ * Synchronises and returns the running energy (sum of accepted dE since the
+ * last re-sum, plus that re-sum) in *e_running, and, if e_exact is not NULL,
+ * a fresh double-precision re-sum of the total energy of the current state
+ * (which does not reset the running energy).  Energies in kT.
+ */
+int mc_energy(mc_handle* h, double* e_running, double* e_exact);
+
+/*
+ * Synchronises and returns the pair correlation functions accumulated so far.
+ * Species are the distinct (charge, diameter) pairs, ordered by decreasing
+ * charge then increasing diameter.  g [ntypes*ntypes*bins] receives
+ * g_ab(r_k) = C_ab(k) / (Ncentre_a * n_b * V_k) (centres: ions with
+ * |x| <= R - rmax; n_b = (N_b - delta_ab) / ((4/3) pi (R - sigma_b/2)^3);
+ * V_k the shell volume); counts (nullable) [ntypes*ntypes*bins] the raw
+ * integer pair counts; centres (nullable) [ntypes] the centre counts; bins
+ * must equal the handle's rdf_bins.  *n_samples (nullable) gets the number of
+ * configurations accumulated.
+ */
+int mc_rdf(mc_handle* h, int32_t bins, double* g, uint64_t* counts, uint64_t* centres,
+           int64_t* n_samples);
+
+/* Enqueues one g(r) sample of the current configuration. */
+int mc_rdf_sample(mc_handle* h);
+
+/* Clears the accumulated g(r) counts. */
+int mc_rdf_reset(mc_handle* h);
+
+/* Number of species and, if the pointers are non-NULL, their charges/diameters. */
+int mc_species(const mc_handle* h, int32_t* ntypes, double* charges, double* diameters);
+
+/* Synchronises and copies the current positions, [n*3] doubles (exact copies
+ * of the stored float or double values). */
+int mc_get_positions(mc_handle* h, double* xyz);
+
+/*
+ * Synchronises and copies the trace of the first moves (see trace_moves):
+ * acc [n_moves] accept bytes, dE [n_moves] doubles (either may be NULL).
+ * n_moves must not exceed the traced capacity nor the moves done so far.
+ */
+int mc_trace(mc_handle* h, int64_t n_moves, uint8_t* acc, double* dE);
+
+/*
+ * Synchronises and copies the per-sweep running energies recorded since the
+ * handle was created (one value after each sweep, sweep index 0 first):
+ * e [n] with n <= number of sweeps done.
+ */
+int mc_energy_series(mc_handle* h, int64_t n, double* e);
+
+typedef struct mc_stats {
+    int64_t sweeps;          /* sweeps done                                        */
+    int64_t moves;           /* trial moves attempted                             */
+    int64_t accepted;        /* accepted moves                                    */
+    int64_t rejected_wall;   /* rejected because the trial crosses the wall        */
+    int64_t rejected_overlap;/* rejected by the hard-core indicator (not wall)     */
+    int64_t rejected_metropolis; /* rejected by the Metropolis test                */
+    int64_t fixpoint_iterations; /* in-group decision iterations (diagnostic)      */
+    int64_t resums;          /* double-precision energy re-sums done               */
+    double last_drift;       /* running minus re-summed energy at the last re-sum  */
+    double max_abs_drift;    /* largest |drift| over all re-sums                   */
+    int32_t band;            /* band width used                                    */
+    int32_t waves;           /* waves per workgroup used                           */
+    int32_t workgroups;      /* workgroups used by the last sweep launch           */
+    int32_t reserved;
+} mc_stats;
+
+/* Synchronises and fills *out. */
+int mc_get_stats(mc_handle* h, mc_stats* out);
+
+/*
+ * Synchronises and reports the device time of the sweep-kernel launches made
+ * since the handle was created or since mc_timing_reset (requires
+ * record_timing): *launches launches (nullable), *kernel_ms their summed
+ * duration in milliseconds (nullable), *sweeps the sweeps they covered
+ * (nullable).  The energy re-sum and g(r) kernels are not included.
+ */
+int mc_timing(mc_handle* h, int64_t* launches, double* kernel_ms, int64_t* sweeps);
+
+/* Clears the timing totals. */
+int mc_timing_reset(mc_handle* h);
+
+/* Changes the trial-cube half side for subsequent sweeps (e.g. after
+ * warm-up tuning); max_disp > 0. */
+int mc_set_max_disp(mc_handle* h, double max_disp);
+
+/* Releases every resource of the handle; NULL is allowed. */
+void mc_destroy(mc_handle* h);
+
+/* Human-readable description of the last error on h (or of the last failed
+ * mc_create when h is NULL).  Never NULL. */
+const char* mc_last_error(const mc_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MC_H_ */

@@ -239,8 +239,8 @@ int64_t orc_sweeps_f64(int32_t n, double* xyz, const double* q, const double* si
 int64_t orc_replay_f32(int32_t n, float* xyz, const double* q, const double* sigma,
                        double R, double lB, float D, uint64_t seed, uint32_t chain,
                        uint32_t sweep0, int64_t n_moves, const uint8_t* acc_given,
-                       double* de_out, double* u3_out, uint8_t* flags_out,
-                       uint8_t* own_out)
+                       const uint8_t* eval_mask, double* de_out, double* u3_out,
+                       uint8_t* flags_out, uint8_t* own_out)
 {
     double* xd = (double*)malloc(sizeof(double) * 3 * (size_t)n);
     if (!xd) return -1;
@@ -261,11 +261,16 @@ int64_t orc_replay_f32(int32_t n, float* xyz, const double* q, const double* sig
         double xt[3] = {(double)xtf[0], (double)xtf[1], (double)xtf[2]};
         int wall = outside_wall(xt, R, sigma[i]);
         int ov = 0;
-        double dE = orc_delta_energy(n, xd, q, sigma, i, xt, lB, &ov);
         double u3 = (double)w[3] * 0x1p-32;
-        int own = !wall && !ov && metropolis(dE, u3);
+        int evaluate = !eval_mask || eval_mask[m] || !acc_given;
+        double dE = 0.0;
+        int own = 0;
+        if (evaluate) {
+            dE = orc_delta_energy(n, xd, q, sigma, i, xt, lB, &ov);
+            own = !wall && !ov && metropolis(dE, u3);
+        }
         int acc = acc_given ? (int)acc_given[m] : own;
-        if (acc != own) ++mismatches;
+        if (evaluate && acc != own) ++mismatches;
         if (de_out) de_out[m] = dE;
         if (u3_out) u3_out[m] = u3;
         if (flags_out) flags_out[m] = (uint8_t)(wall | (ov << 1));

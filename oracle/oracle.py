@@ -74,7 +74,7 @@ def lib():
         L.orc_replay_f32.argtypes = [ctypes.c_int32, _f32p, _f64p, _f64p, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_float, ctypes.c_uint64,
                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64, _u8p,
-                                     _f64p, _f64p, _u8p, _u8p]
+                                     _u8p, _f64p, _f64p, _u8p, _u8p]
         L.orc_replay_f32.restype = ctypes.c_int64
         L.orc_rdf_counts.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int32,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_int32, _u64p,
@@ -170,11 +170,12 @@ class Chain:
         return out
 
 
-def replay_f32(xyz_f32, q, sigma, R, lB, D, seed, chain, sweep0, n_moves, acc_given=None):
+def replay_f32(xyz_f32, q, sigma, R, lB, D, seed, chain, sweep0, n_moves, acc_given=None,
+               eval_mask=None):
     """Exact double dE of each move along a float-state trajectory.
 
     The trajectory follows ``acc_given`` (e.g. another implementation's
-    decisions); returns dict with dE, u3, flags (bit0 wall, bit1 overlap),
+    decisions); with ``eval_mask`` only the marked moves are evaluated.  Returns dict with dE, u3, flags (bit0 wall, bit1 overlap),
     the oracle's own decision per move, the final float state and the number
     of moves whose given decision differs from the oracle's.
     """
@@ -187,10 +188,11 @@ def replay_f32(xyz_f32, q, sigma, R, lB, D, seed, chain, sweep0, n_moves, acc_gi
     fl = np.zeros(n_moves, np.uint8)
     own = np.zeros(n_moves, np.uint8)
     ag = None if acc_given is None else np.ascontiguousarray(acc_given, np.uint8)
+    em = None if eval_mask is None else np.ascontiguousarray(eval_mask, np.uint8)
     mism = lib().orc_replay_f32(n, _p(x, _f32p), _p(qq, _f64p), _p(ss, _f64p), R, lB,
                                 np.float32(D), seed, chain, sweep0, int(n_moves),
-                                _p(ag, _u8p), _p(de, _f64p), _p(u3, _f64p), _p(fl, _u8p),
-                                _p(own, _u8p))
+                                _p(ag, _u8p), _p(em, _u8p), _p(de, _f64p), _p(u3, _f64p),
+                                _p(fl, _u8p), _p(own, _u8p))
     return {"dE": de, "u3": u3, "flags": fl, "own": own, "xyz": x, "mismatches": int(mism)}
 
 

@@ -1,0 +1,162 @@
+// mc_device.hpp -- device-side building blocks shared by the gfx950 kernels:
+// precision traits, the Philox4x32-10 generator, the trial-move formulas and
+// the device-wide wait / publish primitives.
+//
+// Paper: Liang, Xing, Li, arXiv:1602.05716.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcdev {
+
+constexpr int kGroup = 64;   // movers per group = lanes of one wavefront
+constexpr int kRing = 64;    // group records kept per chain (must exceed the band)
+constexpr int kMaxBand = 4;  // largest look-ahead band, in groups
+
+// Per-group record published by the workgroup that decided the group.
+struct GroupRec {
+    int64_t tag;     // stream index + 1 of the group held in this slot
+    uint64_t acc;    // accept mask of the group's 64 trials
+    double e_run;    // running total energy after the group's trials
+    double spare;
+};
+
+// Status words shared by every workgroup of a launch.
+struct Ctl {
+    int* abort;              // set to a nonzero mc_status on a fatal device condition
+    uint64_t timeout_ticks;  // limit of one wait, in wall_clock64() ticks
+};
+
+// --------------------------------------------------------------------------
+// Precision traits.  The float path keeps positions in float4 {x, y, z, q}
+// (the paper's X_dev layout, Sec. 3.1) and evaluates pair terms with the
+// hardware reciprocal square root; the double path uses correctly rounded
+// sqrt and division so that every pair term equals the textbook value.
+// --------------------------------------------------------------------------
+template <typename T> struct Prec;
+
+template <> struct Prec<float> {
+    using T4 = float4;
+    static __device__ __forceinline__ float rinv(float d2) { return __builtin_amdgcn_rsqf(d2); }
+    // d2 = dx^2 + dy^2 + dz^2 with fused multiply-adds
+    static __device__ __forceinline__ float norm2(float dx, float dy, float dz) {
+        return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+    }
+    static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+};
+
+template <> struct Prec<double> {
+    using T4 = double4;
+    static __device__ __forceinline__ double rinv(double d2) { return 1.0 / __builtin_sqrt(d2); }
+    // left-to-right sum of three rounded squares, no fused multiply-add
+    static __device__ __forceinline__ double norm2(double dx, double dy, double dz) {
+        return dx * dx + dy * dy + dz * dz;
+    }
+    // the double path keeps the textbook rounding: product, then sum
+    static __device__ __forceinline__ double fma(double a, double b, double c) { return a * b + c; }
+};
+
+template <typename T>
+__device__ __forceinline__ typename Prec<T>::T4 mk4(T x, T y, T z, T w) {
+    typename Prec<T>::T4 v;
+    v.x = x; v.y = y; v.z = z; v.w = w;
+    return v;
+}
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 32x32 -> 64-bit products; the key is bumped by the Weyl constants between
+// rounds.  One block per trial move: counter (i, sweep, chain, tag), key
+// (seed low word, seed high word).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a0 = 0xD2511F53u * c.x, h0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t a1 = 0xCD9E8D57u * c.z, h1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(h1 ^ c.y ^ k0, a1, h0 ^ c.w ^ k1, a0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint4 move_words(uint64_t seed, uint32_t chain, uint32_t sweep,
+                                            uint32_t ion) {
+    return philox4x32_10(make_uint4(ion, sweep, chain, 0u), (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// Trial coordinate x + D (u - 1/2) (Sec. 3.2, Algorithm 1), every step rounded
+// in the working precision (build with contraction off).
+__device__ __forceinline__ float trial_coord(float x, uint32_t w, float D) {
+    float u = (float)(w >> 8) * 0x1p-24f;
+    float t = u - 0.5f;
+    t = D * t;
+    return x + t;
+}
+__device__ __forceinline__ double trial_coord(double x, uint32_t w, double D) {
+    double u = (double)w * 0x1p-32;
+    double t = u - 0.5;
+    t = D * t;
+    return x + t;
+}
+
+__device__ __forceinline__ double accept_uniform(uint32_t w) { return (double)w * 0x1p-32; }
+
+// --------------------------------------------------------------------------
+// Device-wide ordering.  A group's decisions become visible through a
+// per-chain "front" counter (number of groups decided, in stream order),
+// stored with release semantics at agent scope after the positions and the
+// group record; readers load it and then acquire at agent scope.  Agent
+// scope is required: the 8 XCDs of the device have separate L2 caches.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int64_t load_front(const uint64_t* front) {
+    return (int64_t)__hip_atomic_load(front, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until *front >= need.  `known` caches the largest value seen, so a
+// satisfied wait costs nothing.  Returns false if the launch is aborting (the
+// caller then proceeds without the data; its results are discarded).
+__device__ __forceinline__ bool wait_front(const uint64_t* front, int64_t need, int64_t& known,
+                                           const Ctl& ctl) {
+    if (known >= need) return true;
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        const int64_t f = load_front(front);
+        if (f >= need) {
+            known = f;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return true;
+        }
+        if (__hip_atomic_load(ctl.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+            return false;
+        if (wall_clock64() - t0 > ctl.timeout_ticks) {
+            int expected = 0;
+            __hip_atomic_compare_exchange_strong(ctl.abort, &expected, -7 /* MC_E_TIMEOUT */,
+                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Orders this wave's LDS accesses for other lanes of the same wave.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
+    return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace mcdev

@@ -1,0 +1,233 @@
+"""Thin ctypes binding of the C ABI in include/mc.h (libmc.so, HIP, gfx950).
+
+Argument marshalling only: every step of the Monte Carlo path runs in the
+library's kernels.  Importing this module loads the library and raises
+``MCLibraryError`` if it is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmc.so")
+
+MC_OK = 0
+STATUS = {0: "MC_OK", -1: "MC_E_ARG", -2: "MC_E_OVERLAP", -3: "MC_E_WALL", -4: "MC_E_NOT_NEUTRAL",
+          -5: "MC_E_DEVICE", -6: "MC_E_OOM", -7: "MC_E_TIMEOUT", -8: "MC_E_STATE"}
+MC_FP64 = 0
+MC_FP32_ACC64 = 1
+
+
+class MCLibraryError(RuntimeError):
+    pass
+
+
+class MCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_disp", ctypes.c_double),
+                ("resum_every", ctypes.c_int32), ("rdf_every", ctypes.c_int32),
+                ("rdf_bins", ctypes.c_int32), ("rdf_rmax", ctypes.c_double),
+                ("chain_id", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p),
+                ("band", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("workgroups", ctypes.c_int32), ("trace_moves", ctypes.c_int64),
+                ("wait_timeout_s", ctypes.c_double), ("record_timing", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("moves", ctypes.c_int64), ("accepted", ctypes.c_int64),
+                ("rejected_wall", ctypes.c_int64), ("rejected_overlap", ctypes.c_int64),
+                ("rejected_metropolis", ctypes.c_int64), ("fixpoint_iterations", ctypes.c_int64),
+                ("resums", ctypes.c_int64), ("last_drift", ctypes.c_double),
+                ("max_abs_drift", ctypes.c_double), ("band", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+# Every symbol include/mc.h declares.
+SYMBOLS = ["mc_options_init", "mc_create", "mc_sweep", "mc_energy", "mc_rdf", "mc_rdf_sample",
+           "mc_rdf_reset", "mc_species", "mc_get_positions", "mc_trace", "mc_energy_series",
+           "mc_get_stats", "mc_timing", "mc_timing_reset", "mc_set_max_disp", "mc_destroy",
+           "mc_last_error"]
+
+_f64p = ctypes.POINTER(ctypes.c_double)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_hp = ctypes.c_void_p
+
+
+def load(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise MCLibraryError("HIP library %s is not built (run __graft_entry__.build())" % path)
+    L = ctypes.CDLL(path)
+    sig = {
+        "mc_options_init": ([ctypes.POINTER(Options)], ctypes.c_int),
+        "mc_create": ([ctypes.c_int32, _f64p, _f64p, _f64p, ctypes.c_double, ctypes.c_double,
+                       ctypes.POINTER(Options), ctypes.POINTER(_hp)], ctypes.c_int),
+        "mc_sweep": ([_hp, ctypes.c_int64, ctypes.c_uint64], ctypes.c_int),
+        "mc_energy": ([_hp, _f64p, _f64p], ctypes.c_int),
+        "mc_rdf": ([_hp, ctypes.c_int32, _f64p, _u64p, _u64p, _i64p], ctypes.c_int),
+        "mc_rdf_sample": ([_hp], ctypes.c_int),
+        "mc_rdf_reset": ([_hp], ctypes.c_int),
+        "mc_species": ([_hp, _i32p, _f64p, _f64p], ctypes.c_int),
+        "mc_get_positions": ([_hp, _f64p], ctypes.c_int),
+        "mc_trace": ([_hp, ctypes.c_int64, _u8p, _f64p], ctypes.c_int),
+        "mc_energy_series": ([_hp, ctypes.c_int64, _f64p], ctypes.c_int),
+        "mc_get_stats": ([_hp, ctypes.POINTER(Stats)], ctypes.c_int),
+        "mc_timing": ([_hp, _i64p, _f64p, _i64p], ctypes.c_int),
+        "mc_timing_reset": ([_hp], ctypes.c_int),
+        "mc_set_max_disp": ([_hp, ctypes.c_double], ctypes.c_int),
+        "mc_destroy": ([_hp], None),
+        "mc_last_error": ([_hp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def options(**kw) -> Options:
+    o = Options()
+    lib().mc_options_init(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": MC_FP64, "fp32": MC_FP32_ACC64}[v]
+        setattr(o, k, v)
+    return o
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+class Chain:
+    """One Markov chain living on the GPU (a handle of the C ABI)."""
+
+    def __init__(self, xyz, q, sigma, R, lB, **opts):
+        self._L = lib()
+        self.q = np.ascontiguousarray(q, np.float64)
+        self.sigma = np.ascontiguousarray(sigma, np.float64)
+        x = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)
+        self.n = len(self.q)
+        self.R, self.lB = float(R), float(lB)
+        self.opt = options(**opts)
+        h = _hp()
+        rc = self._L.mc_create(self.n, _p(self.q, _f64p), _p(self.sigma, _f64p), _p(x, _f64p),
+                               self.R, self.lB, ctypes.byref(self.opt), ctypes.byref(h))
+        if rc != MC_OK:
+            raise MCError(rc, self._L.mc_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != MC_OK:
+            raise MCError(rc, self._L.mc_last_error(self.h).decode())
+
+    def sweep(self, n_sweeps, seed):
+        self._check(self._L.mc_sweep(self.h, int(n_sweeps), int(seed)))
+
+    def energy(self, exact=False):
+        er = ctypes.c_double()
+        ee = ctypes.c_double()
+        self._check(self._L.mc_energy(self.h, ctypes.byref(er), ctypes.byref(ee) if exact else None))
+        return (er.value, ee.value) if exact else er.value
+
+    def positions(self):
+        out = np.zeros((self.n, 3), np.float64)
+        self._check(self._L.mc_get_positions(self.h, _p(out, _f64p)))
+        return out
+
+    def trace(self, n_moves):
+        acc = np.zeros(n_moves, np.uint8)
+        de = np.zeros(n_moves, np.float64)
+        self._check(self._L.mc_trace(self.h, int(n_moves), _p(acc, _u8p), _p(de, _f64p)))
+        return acc, de
+
+    def energy_series(self, n):
+        e = np.zeros(n, np.float64)
+        self._check(self._L.mc_energy_series(self.h, int(n), _p(e, _f64p)))
+        return e
+
+    def species(self):
+        nt = ctypes.c_int32()
+        self._check(self._L.mc_species(self.h, ctypes.byref(nt), None, None))
+        q = np.zeros(nt.value)
+        s = np.zeros(nt.value)
+        self._check(self._L.mc_species(self.h, None, _p(q, _f64p), _p(s, _f64p)))
+        return q, s
+
+    def rdf_sample(self):
+        self._check(self._L.mc_rdf_sample(self.h))
+
+    def rdf_reset(self):
+        self._check(self._L.mc_rdf_reset(self.h))
+
+    def rdf(self):
+        q, _ = self.species()
+        nt = len(q)
+        bins = self.opt.rdf_bins
+        g = np.zeros((nt, nt, bins))
+        c = np.zeros((nt, nt, bins), np.uint64)
+        ce = np.zeros(nt, np.uint64)
+        ns = ctypes.c_int64()
+        self._check(self._L.mc_rdf(self.h, bins, _p(g, _f64p), _p(c, _u64p), _p(ce, _u64p),
+                                   ctypes.byref(ns)))
+        return {"g": g, "counts": c, "centres": ce, "samples": ns.value}
+
+    def stats(self):
+        st = Stats()
+        self._check(self._L.mc_get_stats(self.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def timing(self):
+        """(launches, summed sweep-kernel ms, sweeps covered) from HIP events."""
+        la = ctypes.c_int64()
+        ms = ctypes.c_double()
+        sw = ctypes.c_int64()
+        self._check(self._L.mc_timing(self.h, ctypes.byref(la), ctypes.byref(ms), ctypes.byref(sw)))
+        return la.value, ms.value, sw.value
+
+    def timing_reset(self):
+        self._check(self._L.mc_timing_reset(self.h))
+
+    def set_max_disp(self, v):
+        self._check(self._L.mc_set_max_disp(self.h, float(v)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.mc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
