@@ -18,14 +18,16 @@ struct EnergyAux {
     unsigned long long n_resum;
 };
 
+// Positions are read as {x, y, z, *} records (the fourth word is the sweep
+// version tag of the sweep kernel) and charges from their own array.
 // E = l_B sum_{i<j} q_i q_j / r_ij, every term formed exactly as
 // (q_i q_j) / sqrt(d2) in double.  Block p handles the row groups p and
 // nb-1-p (so every block does nb+1 tiles); wave w of the block takes the
 // tiles t = row + w, row + w + 4, ...  partial[p] receives the block's sum.
 template <typename T>
 __global__ void __launch_bounds__(256)
-energy_partial_kernel(const typename Prec<T>::T4* __restrict__ pos, int nb,
-                      double* __restrict__ partial)
+energy_partial_kernel(const typename Prec<T>::T4* __restrict__ pos, const T* __restrict__ charge,
+                      int nb, double* __restrict__ partial)
 {
     using T4 = typename Prec<T>::T4;
     __shared__ double st[4][kGroup][4];
@@ -38,14 +40,14 @@ energy_partial_kernel(const typename Prec<T>::T4* __restrict__ pos, int nb,
         if (pass == 1 && row == p) break;
         const int i = row * kGroup + lane;
         const T4 xi4 = pos[i];
-        const double xi = (double)xi4.x, yi = (double)xi4.y, zi = (double)xi4.z, qi = (double)xi4.w;
+        const double xi = (double)xi4.x, yi = (double)xi4.y, zi = (double)xi4.z, qi = (double)charge[i];
         double e = 0.0;
         for (int t = row + wave; t < nb; t += 4) {
             const T4 pj = pos[t * kGroup + lane];
             st[wave][lane][0] = (double)pj.x;
             st[wave][lane][1] = (double)pj.y;
             st[wave][lane][2] = (double)pj.z;
-            st[wave][lane][3] = (double)pj.w;
+            st[wave][lane][3] = (double)charge[t * kGroup + lane];
             wave_lds_sync();
             for (int m = 0; m < kGroup; ++m) {
                 const int j = t * kGroup + m;
@@ -67,26 +69,23 @@ energy_partial_kernel(const typename Prec<T>::T4* __restrict__ pos, int nb,
 }
 
 // Sums the block partials in a fixed order, records the drift of the running
-// energy and, when `reset` is set, makes the re-sum the new running energy
-// (written into the record of the last decided group).
+// energy and, when `reset` is set, makes the re-sum the new running energy.
 __global__ void energy_finalize_kernel(const double* __restrict__ partial, int nparts, double lB,
-                                       GroupRec* rec, int64_t g_last, EnergyAux* aux, int reset,
-                                       int record_drift)
+                                       double* e_state, EnergyAux* aux, int reset, int record_drift)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double e = 0.0;
     for (int k = 0; k < nparts; ++k) e += partial[k];
     e *= lB;
     aux->e_resum = e;
-    GroupRec& r = rec[(size_t)(g_last & (kRing - 1))];
     if (record_drift) {
-        const double d = r.e_run - e;
+        const double d = *e_state - e;
         aux->drift_last = d;
         const double ad = d < 0 ? -d : d;
         if (ad > aux->drift_max) aux->drift_max = ad;
         aux->n_resum += 1;
     }
-    if (reset) r.e_run = e;
+    if (reset) *e_state = e;
 }
 
 // Pair counts for g_ab(r): centre i needs |x_i| <= R - rmax (the wall

@@ -12,14 +12,14 @@ namespace mcdev {
 
 constexpr int kGroup = 64;   // movers per group = lanes of one wavefront
 constexpr int kRing = 64;    // group records kept per chain (must exceed the band)
-constexpr int kMaxBand = 4;  // largest look-ahead band, in groups
+constexpr int kMaxBand = 2;  // largest look-ahead band, in groups
 
-// Per-group record published by the workgroup that decided the group.
+// Per-group record published by the workgroup that decided the group; one
+// 16-byte transaction, so the tag and the accept mask are read together.
 struct GroupRec {
-    int64_t tag;     // stream index + 1 of the group held in this slot
+    uint32_t tag;    // (stream index + 1) mod 2^32 of the group held in this slot
+    uint32_t spare;
     uint64_t acc;    // accept mask of the group's 64 trials
-    double e_run;    // running total energy after the group's trials
-    double spare;
 };
 
 // Status words shared by every workgroup of a launch.
@@ -105,38 +105,84 @@ __device__ __forceinline__ double trial_coord(double x, uint32_t w, double D) {
 __device__ __forceinline__ double accept_uniform(uint32_t w) { return (double)w * 0x1p-32; }
 
 // --------------------------------------------------------------------------
-// Device-wide ordering.  A group's decisions become visible through a
-// per-chain "front" counter (number of groups decided, in stream order),
-// stored with release semantics at agent scope after the positions and the
-// group record; readers load it and then acquire at agent scope.  Agent
-// scope is required: the 8 XCDs of the device have separate L2 caches.
+// Device-wide communication without cache maintenance.  Everything one
+// workgroup publishes for others (versioned positions, group records) is
+// written and read with agent-coherent 16-byte accesses (the sc1 cache
+// policy: coherent across the separate L2 caches of the 8 XCDs), so no L2
+// write-back or invalidate is ever needed.  Every published record carries
+// its own validity tag, so readers need no separate flag.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ int64_t load_front(const uint64_t* front) {
-    return (int64_t)__hip_atomic_load(front, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+constexpr int kCoherent = 16;  // buffer-instruction cache policy: sc1
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, bytes, 0x00020000);
 }
 
-// Waits until *front >= need.  `known` caches the largest value seen, so a
-// satisfied wait costs nothing.  Returns false if the launch is aborting (the
-// caller then proceeds without the data; its results are discarded).
-__device__ __forceinline__ bool wait_front(const uint64_t* front, int64_t need, int64_t& known,
-                                           const Ctl& ctl) {
-    if (known >= need) return true;
+using u32x4 = __attribute__((ext_vector_type(4))) unsigned int;
+
+__device__ __forceinline__ float4 coherent_load(__amdgpu_buffer_rsrc_t r, uint32_t idx, float4*) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, idx * 16u, 0, kCoherent));
+}
+__device__ __forceinline__ double4 coherent_load(__amdgpu_buffer_rsrc_t r, uint32_t idx, double4*) {
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, idx * 32u, 0, kCoherent);
+    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, idx * 32u + 16u, 0, kCoherent);
+    const double2 lo = __builtin_bit_cast(double2, a), hi = __builtin_bit_cast(double2, b);
+    return make_double4(lo.x, lo.y, hi.x, hi.y);
+}
+__device__ __forceinline__ void coherent_store(__amdgpu_buffer_rsrc_t r, uint32_t idx, float4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, idx * 16u, 0, kCoherent);
+}
+__device__ __forceinline__ void coherent_store(__amdgpu_buffer_rsrc_t r, uint32_t idx, double4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, make_double2(v.x, v.y)), r,
+                                           idx * 32u, 0, kCoherent);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, make_double2(v.z, v.w)), r,
+                                           idx * 32u + 16u, 0, kCoherent);
+}
+__device__ __forceinline__ GroupRec load_rec(__amdgpu_buffer_rsrc_t r, uint32_t slot) {
+    return __builtin_bit_cast(GroupRec, __builtin_amdgcn_raw_buffer_load_b128(r, slot * 16u, 0, kCoherent));
+}
+__device__ __forceinline__ void store_rec(__amdgpu_buffer_rsrc_t r, uint32_t slot, GroupRec v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, slot * 16u, 0, kCoherent);
+}
+
+// Compiler-level barrier: no memory access moves across it.
+__device__ __forceinline__ void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
+// Waits until every memory access this wave has issued is complete.
+__device__ __forceinline__ void drain_memory() {
+    compiler_fence();
+    __builtin_amdgcn_s_waitcnt(0);
+    compiler_fence();
+}
+
+__device__ __forceinline__ bool abort_raised(const Ctl& ctl) {
+    return __hip_atomic_load(ctl.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+__device__ __forceinline__ void raise_timeout(const Ctl& ctl) {
+    int expected = 0;
+    __hip_atomic_compare_exchange_strong(ctl.abort, &expected, -7 /* MC_E_TIMEOUT */, __ATOMIC_RELAXED,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits for the record of group gp and returns it.  A record only carries the
+// group's accept mask (positions carry their own version tags).  Callers only
+// ask for groups still in the ring (the band), so the slot holds exactly
+// group gp once its tag matches.
+__device__ __forceinline__ GroupRec wait_rec(__amdgpu_buffer_rsrc_t rr, int64_t gp, const Ctl& ctl) {
+    const uint32_t slot = (uint32_t)(gp & (kRing - 1));
+    const uint32_t want = (uint32_t)(gp + 1);
     const uint64_t t0 = wall_clock64();
     for (;;) {
-        const int64_t f = load_front(front);
-        if (f >= need) {
-            known = f;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            return true;
+        const GroupRec r = load_rec(rr, slot);
+        if ((int32_t)(r.tag - want) >= 0) {
+            compiler_fence();
+            return r;
         }
-        if (__hip_atomic_load(ctl.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-            return false;
+        if (abort_raised(ctl)) return r;
         if (wall_clock64() - t0 > ctl.timeout_ticks) {
-            int expected = 0;
-            __hip_atomic_compare_exchange_strong(ctl.abort, &expected, -7 /* MC_E_TIMEOUT */,
-                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-            return false;
+            raise_timeout(ctl);
+            return r;
         }
         __builtin_amdgcn_s_sleep(1);
     }

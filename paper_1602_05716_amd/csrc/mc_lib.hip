@@ -102,10 +102,10 @@ struct mc_handle {
     // device memory
     void* pos = nullptr;          // T4[2][npad]
     void* half = nullptr;         // T[npad]
+    void* charge = nullptr;       // T[npad]
     double* wall_a = nullptr;     // [npad]
     int32_t* d_type = nullptr;    // [npad]
     GroupRec* rec = nullptr;      // [kRing]
-    uint64_t* front = nullptr;
     unsigned long long* stats = nullptr;  // [ST_N]
     int* abort_flag = nullptr;
     double* e_series = nullptr;
@@ -115,6 +115,10 @@ struct mc_handle {
     int64_t trace_cap = 0;
     double* e_partial = nullptr;  // [nb]
     EnergyAux* aux = nullptr;
+    double* e_state = nullptr;    // running energy
+    double* de_group = nullptr;   // [de_capacity] group energy changes of one launch
+    double* sweep_tot = nullptr;  // [max_launch_sweeps]
+    int64_t de_capacity = 0;
     unsigned long long* rdf_counts = nullptr;
     unsigned long long* rdf_centres = nullptr;
     ChainDesc* d_desc = nullptr;
@@ -169,9 +173,10 @@ void drop_events(mc_handle* h) {
 
 void free_all(mc_handle* h) {
     drop_events(h);
-    void* bufs[] = {h->pos, h->half, h->wall_a, h->d_type, h->rec, h->front, h->stats,
+    void* bufs[] = {h->pos, h->half, h->charge, h->wall_a, h->d_type, h->rec, h->stats,
                     h->abort_flag, h->e_series, h->trace_acc, h->trace_de, h->e_partial, h->aux,
-                    h->rdf_counts, h->rdf_centres, h->d_desc, h->d_wgmap};
+                    h->e_state, h->de_group, h->sweep_tot, h->rdf_counts, h->rdf_centres,
+                    h->d_desc, h->d_wgmap};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -248,9 +253,7 @@ int ensure_series(mc_handle* h, int64_t need) {
     }
     h->e_series = nb;
     h->e_capacity = cap;
-    h->desc.e_series = nb;
-    h->desc.e_capacity = cap;
-    return upload_desc(h);
+    return MC_OK;
 }
 
 int launch_energy(mc_handle* h, int reset, int record_drift) {
@@ -260,14 +263,13 @@ int launch_energy(mc_handle* h, int reset, int record_drift) {
     const void* p = (const char*)h->pos + (size_t)parity * h->npad * t4;
     if (h->fp64)
         hipLaunchKernelGGL(energy_partial_kernel<double>, dim3(nparts), dim3(256), 0, h->stream,
-                           (const double4*)p, h->nb, h->e_partial);
+                           (const double4*)p, (const double*)h->charge, h->nb, h->e_partial);
     else
         hipLaunchKernelGGL(energy_partial_kernel<float>, dim3(nparts), dim3(256), 0, h->stream,
-                           (const float4*)p, h->nb, h->e_partial);
+                           (const float4*)p, (const float*)h->charge, h->nb, h->e_partial);
     HIPCHECK(h, hipGetLastError());
-    const int64_t g_last = h->sweeps * (int64_t)h->nb - 1;
     hipLaunchKernelGGL(energy_finalize_kernel, dim3(1), dim3(64), 0, h->stream, h->e_partial, nparts,
-                       h->lB, h->rec, g_last, h->aux, reset, record_drift);
+                       h->lB, h->e_state, h->aux, reset, record_drift);
     HIPCHECK(h, hipGetLastError());
     return MC_OK;
 }
@@ -293,10 +295,28 @@ int launch_rdf(mc_handle* h) {
     return MC_OK;
 }
 
+constexpr int64_t kMaxLaunchSweeps = 4096;
+
 int launch_sweeps(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
     if (n_sweeps <= 0) return MC_OK;
+    if (n_sweeps > kMaxLaunchSweeps) {
+        int rc = launch_sweeps(h, kMaxLaunchSweeps, seed);
+        if (rc) return rc;
+        return launch_sweeps(h, n_sweeps - kMaxLaunchSweeps, seed);
+    }
     int rc = ensure_series(h, h->sweeps + n_sweeps);
     if (rc) return rc;
+    const int64_t ngroups = n_sweeps * (int64_t)h->nb;
+    if (ngroups > h->de_capacity) {
+        HIPCHECK(h, hipStreamSynchronize(h->stream));
+        if (h->de_group) (void)hipFree(h->de_group);
+        h->de_group = nullptr;
+        h->de_capacity = 0;
+        if ((rc = dalloc(h, &h->de_group, sizeof(double) * ngroups))) return rc;
+        h->de_capacity = ngroups;
+        h->desc.de_group = h->de_group;
+        if ((rc = upload_desc(h))) return rc;
+    }
     if (h->desc.seed != seed) {
         h->desc.seed = seed;
         if ((rc = upload_desc(h))) return rc;
@@ -323,6 +343,10 @@ int launch_sweeps(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
         h->ev_pending.emplace_back(e0, e1);
         h->ev_sweeps.push_back(n_sweeps);
     }
+    hipLaunchKernelGGL(energy_scan_kernel, dim3(1), dim3(256), 0, h->stream, h->de_group, h->nb,
+                       (int32_t)n_sweeps, (int64_t)h->sweeps, h->sweep_tot, h->e_state, h->e_series,
+                       h->e_capacity);
+    HIPCHECK(h, hipGetLastError());
     h->sweeps += n_sweeps;
     return MC_OK;
 }
@@ -467,12 +491,15 @@ int mc_create(int32_t n, const double* charges, const double* diameters, const d
     const size_t t4 = h->fp64 ? sizeof(double4) : sizeof(float4);
     const size_t t1 = h->fp64 ? sizeof(double) : sizeof(float);
     if ((rc = dalloc(h, &h->pos, 2 * t4 * h->npad)) || (rc = dalloc(h, &h->half, t1 * h->npad)) ||
+        (rc = dalloc(h, &h->charge, t1 * h->npad)) ||
         (rc = dalloc(h, &h->wall_a, sizeof(double) * h->npad)) ||
         (rc = dalloc(h, &h->d_type, sizeof(int32_t) * h->npad)) ||
-        (rc = dalloc(h, &h->rec, sizeof(GroupRec) * kRing)) || (rc = dalloc(h, &h->front, sizeof(uint64_t))) ||
+        (rc = dalloc(h, &h->rec, sizeof(GroupRec) * kRing)) ||
         (rc = dalloc(h, &h->stats, sizeof(unsigned long long) * ST_N)) ||
         (rc = dalloc(h, &h->abort_flag, sizeof(int))) ||
         (rc = dalloc(h, &h->e_partial, sizeof(double) * h->nb)) || (rc = dalloc(h, &h->aux, sizeof(EnergyAux))) ||
+        (rc = dalloc(h, &h->e_state, sizeof(double))) ||
+        (rc = dalloc(h, &h->sweep_tot, sizeof(double) * kMaxLaunchSweeps)) ||
         (rc = dalloc(h, &h->d_desc, sizeof(ChainDesc))))
         return bail(rc);
     const size_t nt = h->species.size();
@@ -487,8 +514,10 @@ int mc_create(int32_t n, const double* charges, const double* diameters, const d
             return bail(rc);
     }
 
-    // host images
-    std::vector<char> hpos(t4 * h->npad), hhalf(t1 * h->npad);
+    // host images: positions carry the version tag of the sweep that produced
+    // them; the initial state is the result of virtual sweeps -2 (parity 0)
+    // and -1 (parity 1)
+    std::vector<char> hpos(2 * t4 * h->npad), hhalf(t1 * h->npad), hq(t1 * h->npad);
     std::vector<double> hwall(h->npad, 0.0);
     for (int i = 0; i < h->npad; ++i) {
         double x, y, z, qq, hh;
@@ -507,40 +536,48 @@ int mc_create(int32_t n, const double* charges, const double* diameters, const d
             qq = 0.0;
             hh = 0.0;
         }
+        for (int par = 0; par < 2; ++par) {
+            const uint32_t ver = par == 0 ? 0xFFFFFFFEu : 0xFFFFFFFFu;
+            char* dst = &hpos[t4 * ((size_t)par * h->npad + i)];
+            if (h->fp64) {
+                struct { double x, y, z; uint32_t ver, pad; } r{x, y, z, ver, 0u};
+                std::memcpy(dst, &r, t4);
+            } else {
+                struct { float x, y, z; uint32_t ver; } r{(float)x, (float)y, (float)z, ver};
+                std::memcpy(dst, &r, t4);
+            }
+        }
         if (h->fp64) {
-            double4 v = make_double4(x, y, z, qq);
-            std::memcpy(&hpos[t4 * i], &v, t4);
             std::memcpy(&hhalf[t1 * i], &hh, t1);
+            std::memcpy(&hq[t1 * i], &qq, t1);
         } else {
-            float4 v = make_float4((float)x, (float)y, (float)z, (float)qq);
-            float hf = (float)hh;
-            std::memcpy(&hpos[t4 * i], &v, t4);
+            float hf = (float)hh, qf = (float)qq;
             std::memcpy(&hhalf[t1 * i], &hf, t1);
+            std::memcpy(&hq[t1 * i], &qf, t1);
         }
     }
     std::vector<GroupRec> hrec(kRing);
     for (int k = 0; k < kRing; ++k) {
         const int64_t g = (int64_t)k - kRing;  // virtual groups -64..-1: decided, nothing accepted
-        hrec[(size_t)(g & (kRing - 1))] = GroupRec{g + 1, 0ull, 0.0, 0.0};
+        hrec[(size_t)(g & (kRing - 1))] = GroupRec{(uint32_t)(g + 1), 0u, 0ull};
     }
     auto up = [&](void* dst, const void* src, size_t bytes) {
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream);
     };
     std::vector<unsigned long long> zeros(std::max<size_t>(nh, ST_N), 0ull);
     int zero = 0;
-    uint64_t zero64 = 0;
     EnergyAux zaux{0.0, 0.0, 0.0, 0ull};
     hipError_t e = hipSuccess;
-    if ((e = up(h->pos, hpos.data(), t4 * h->npad)) != hipSuccess ||
-        (e = up((char*)h->pos + t4 * h->npad, hpos.data(), t4 * h->npad)) != hipSuccess ||
+    if ((e = up(h->pos, hpos.data(), 2 * t4 * h->npad)) != hipSuccess ||
         (e = up(h->half, hhalf.data(), t1 * h->npad)) != hipSuccess ||
+        (e = up(h->charge, hq.data(), t1 * h->npad)) != hipSuccess ||
         (e = up(h->wall_a, hwall.data(), sizeof(double) * h->npad)) != hipSuccess ||
         (e = up(h->d_type, h->type.data(), sizeof(int32_t) * h->npad)) != hipSuccess ||
         (e = up(h->rec, hrec.data(), sizeof(GroupRec) * kRing)) != hipSuccess ||
-        (e = up(h->front, &zero64, sizeof(uint64_t))) != hipSuccess ||
         (e = up(h->stats, zeros.data(), sizeof(unsigned long long) * ST_N)) != hipSuccess ||
         (e = up(h->abort_flag, &zero, sizeof(int))) != hipSuccess ||
         (e = up(h->aux, &zaux, sizeof(EnergyAux))) != hipSuccess ||
+        (e = up(h->e_state, &zaux.e_resum, sizeof(double))) != hipSuccess ||
         (e = up(h->rdf_counts, zeros.data(), sizeof(unsigned long long) * nh)) != hipSuccess ||
         (e = up(h->rdf_centres, zeros.data(), sizeof(unsigned long long) * nt)) != hipSuccess) {
         h->err = std::string("upload failed: ") + hipGetErrorString(e);
@@ -561,6 +598,15 @@ int mc_create(int32_t n, const double* charges, const double* diameters, const d
         h->err = "occupancy query failed for the sweep kernel";
         return bail(MC_E_DEVICE);
     }
+    // Every workgroup of the cooperative grid must be resident at once.  The
+    // occupancy query has been seen to over-promise for workgroups with more
+    // than 64 KiB of LDS: such kernels get one workgroup per CU.
+    // Kernels that spill to scratch have been seen to run fewer workgroups at
+    // once than the query reports: they also get one workgroup per CU.
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, (const void*)fn) == hipSuccess &&
+        (fa.sharedSizeBytes > 64 * 1024 || fa.localSizeBytes > 0))
+        per_cu = 1;
     const int cap = per_cu * h->dev.cus;
     h->wg = opt.workgroups > 0 ? opt.workgroups : h->nb;
     h->wg = std::max(1, std::min({h->wg, h->nb, cap}));
@@ -577,13 +623,12 @@ int mc_create(int32_t n, const double* charges, const double* diameters, const d
     d.D = h->D;
     d.half_uniform = 0.5 * diameters[0];
     d.pos = h->pos;
+    d.charge = h->charge;
     d.half = h->half;
     d.wall_a = h->wall_a;
     d.rec = h->rec;
-    d.front = h->front;
     d.stats = h->stats;
-    d.e_series = nullptr;
-    d.e_capacity = 0;
+    d.de_group = nullptr;
     d.trace_acc = h->trace_acc;
     d.trace_de = h->trace_de;
     d.trace_cap = h->trace_cap;
@@ -596,7 +641,7 @@ int mc_create(int32_t n, const double* charges, const double* diameters, const d
         return bail(MC_E_DEVICE);
     }
     if ((rc = ensure_series(h, 1024))) return bail(rc);
-    // initial energy: re-sum into the record of virtual group -1
+    // initial energy: re-sum into the running energy
     if ((rc = launch_energy(h, 1, 0))) return bail(rc);
     if ((rc = sync_check(h))) return bail(rc);
     *out = h;
@@ -627,10 +672,7 @@ int mc_energy(mc_handle* h, double* e_running, double* e_exact) {
     if (!h || !e_running) return h ? fail(h, MC_E_ARG, "null output") : MC_E_ARG;
     int rc = sync_check(h);
     if (rc) return rc;
-    const int64_t g_last = h->sweeps * (int64_t)h->nb - 1;
-    GroupRec r;
-    HIPCHECK(h, hipMemcpy(&r, h->rec + (size_t)(g_last & (kRing - 1)), sizeof(GroupRec), hipMemcpyDeviceToHost));
-    *e_running = r.e_run;
+    HIPCHECK(h, hipMemcpy(e_running, h->e_state, sizeof(double), hipMemcpyDeviceToHost));
     if (e_exact) {
         if ((rc = launch_energy(h, 0, 0))) return rc;
         if ((rc = sync_check(h))) return rc;

@@ -12,24 +12,30 @@
 //     stream index g = s*B + b, and the trials form one sequence over g.
 //   * Each target group g is served by one workgroup of M waves.  Lane i of
 //     every wave is mover i of the group; wave w takes a 64/M-ion slice of
-//     every partner group.  This is the paper's "brush" (Sec. 3.4) turned so
-//     that the partner index is uniform across the wave.
+//     every partner group.  This is
+//     the paper's "brush" (Sec. 3.4) turned so that the partner index is
+//     uniform across the wave.
 //   * By Eq. (Delta E_ij) the term of partner j is final as soon as j's own
 //     latest trial is decided.  Partner groups decided more than `band`
 //     groups before g are summed directly with their published positions, in
-//     stream order, as they get decided (this is the upper/lower triangle
-//     split of Sec. 2 applied continuously across sweep boundaries).
+//     stream order, as they get decided (the upper/lower triangle split of
+//     Sec. 2 applied continuously across sweep boundaries).
 //   * For the last `band` groups and for the mover's own group, both possible
 //     outcomes of partner j are evaluated ahead of time (old position and
 //     trial position), so that once j's accept bit is known only a select and
 //     an add remain on the critical path.
-//   * Inside the own group the accept bits are found by iterating the
-//     sequential rule a_i = f_i(a_0..a_{i-1}) to its fixed point (Jacobi
-//     sweeps over the wave); the fixed point is unique and equals the
-//     sequential outcome, reached in at most 64 iterations, usually two.
-//   * The deciding wave writes the group's new positions in place (double
-//     buffered by sweep parity), its accept mask and the running energy, and
-//     advances the chain's front counter with release semantics.
+//   * The waves hand their partial sums and candidate corrections over
+//     through LDS and move on to their next target; wave 0 then waits for
+//     group g-1's accept mask, then finds the group's own accept bits by iterating
+//     the sequential rule a_i = f_i(a_0..a_{i-1}) to its fixed point (Jacobi
+//     sweeps over the wave; the fixed point is unique, equals the sequential
+//     outcome and is reached in at most 64 iterations, usually two).
+//   * Publication: the accept mask goes out at once in the group record; the
+//     new positions are written in place, double buffered by sweep parity,
+//     each 16-byte record carrying the sweep index of the trial that produced
+//     it in its fourth word, so a reader validates every record it loads and
+//     no device-wide counter or cache flush is needed (agent-coherent
+//     accesses only).
 #pragma once
 
 #include "mc_device.hpp"
@@ -48,40 +54,333 @@ struct ChainDesc {
     double lB;           // Bjerrum length
     double D;            // trial cube side
     double half_uniform; // sigma/2 when every ion has the same diameter
-    void* pos;           // T4[2][npad]: positions by sweep parity, w = charge
+    void* pos;           // versioned positions by sweep parity (see PosIO)
+    void* charge;        // T[npad]: q_i
     void* half;          // T[npad]: sigma_i / 2
     const double* wall_a;// double[npad]: R - sigma_i / 2
     GroupRec* rec;       // [kRing]
-    uint64_t* front;     // groups decided (stream index of the next group)
     unsigned long long* stats;  // [8] counters, see mc_host
-    double* e_series;    // [capacity] running energy after each sweep (global sweep index)
-    int64_t e_capacity;
+    double* de_group;    // [launch groups] energy change of each group of the launch
     uint8_t* trace_acc;  // [trace_cap]
     double* trace_de;    // [trace_cap]
     int64_t trace_cap;   // moves traced from the start of the chain
 };
 
+// A position record is {x, y, z, version}: version = sweep index (mod 2^32)
+// of the trial that produced the position; slot pos[s & 1][i] holds the
+// result of trial (s, i).  Float path: one 16-byte record.  Double path: two
+// 16-byte halves {x, y}, {z, version}; the writer drains the first half
+// before storing the second and the reader validates the second half before
+// loading the first.
+template <typename T> struct PosIO;
+
+template <> struct PosIO<float> {
+    struct Rec { float x, y, z; uint32_t ver; };
+    static constexpr uint32_t kBytes = 16;
+    static __device__ __forceinline__ Rec load(__amdgpu_buffer_rsrc_t r, uint32_t idx) {
+        return __builtin_bit_cast(Rec, __builtin_amdgcn_raw_buffer_load_b128(r, idx * 16u, 0, kCoherent));
+    }
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t idx, float x, float y,
+                                                 float z, uint32_t ver) {
+        Rec v{x, y, z, ver};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, idx * 16u, 0, kCoherent);
+    }
+    // loads slot idx until its version is `ver` (all lanes with `active`)
+    static __device__ __forceinline__ Rec load_valid(__amdgpu_buffer_rsrc_t r, uint32_t idx, uint32_t ver,
+                                                     bool active, const Ctl& ctl) {
+        Rec v{0.f, 0.f, 0.f, ver};
+        if (active) v = load(r, idx);
+        if (__ballot(active && v.ver != ver) == 0ull) return v;
+        const uint64_t t0 = wall_clock64();
+        for (;;) {
+            __builtin_amdgcn_s_sleep(1);
+            if (active && v.ver != ver) v = load(r, idx);
+            if (__ballot(active && v.ver != ver) == 0ull) break;
+            if (abort_raised(ctl)) break;
+            if (wall_clock64() - t0 > ctl.timeout_ticks) {
+                raise_timeout(ctl);
+                break;
+            }
+        }
+        return v;
+    }
+};
+
+template <> struct PosIO<double> {
+    struct Rec { double x, y, z; uint32_t ver, pad; };
+    struct Lo { double x, y; };
+    struct Hi { double z; uint32_t ver, pad; };
+    static constexpr uint32_t kBytes = 32;
+    static __device__ __forceinline__ Hi load_hi(__amdgpu_buffer_rsrc_t r, uint32_t idx) {
+        return __builtin_bit_cast(Hi, __builtin_amdgcn_raw_buffer_load_b128(r, idx * 32u + 16u, 0, kCoherent));
+    }
+    static __device__ __forceinline__ Lo load_lo(__amdgpu_buffer_rsrc_t r, uint32_t idx) {
+        return __builtin_bit_cast(Lo, __builtin_amdgcn_raw_buffer_load_b128(r, idx * 32u, 0, kCoherent));
+    }
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t idx, double x, double y,
+                                                 double z, uint32_t ver) {
+        Lo lo{x, y};
+        Hi hi{z, ver, 0u};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, lo), r, idx * 32u, 0, kCoherent);
+        drain_memory();
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, hi), r, idx * 32u + 16u, 0, kCoherent);
+    }
+    static __device__ __forceinline__ Rec load_valid(__amdgpu_buffer_rsrc_t r, uint32_t idx, uint32_t ver,
+                                                     bool active, const Ctl& ctl) {
+        Hi h{0.0, ver, 0u};
+        if (active) h = load_hi(r, idx);
+        if (__ballot(active && h.ver != ver) != 0ull) {
+            const uint64_t t0 = wall_clock64();
+            for (;;) {
+                __builtin_amdgcn_s_sleep(1);
+                if (active && h.ver != ver) h = load_hi(r, idx);
+                if (__ballot(active && h.ver != ver) == 0ull) break;
+                if (abort_raised(ctl)) break;
+                if (wall_clock64() - t0 > ctl.timeout_ticks) {
+                    raise_timeout(ctl);
+                    break;
+                }
+            }
+        }
+        drain_memory();  // the high half is validated before the low half is read
+        Lo l{0.0, 0.0};
+        if (active) l = load_lo(r, idx);
+        return Rec{l.x, l.y, h.z, h.ver, 0u};
+    }
+};
+
+// Bit masks over one wave's slice of a partner group.
+template <int P> struct SliceBits;
+template <> struct SliceBits<8> { using type = uint8_t; };
+template <> struct SliceBits<16> { using type = uint16_t; };
+
 template <typename T, int M>
 struct SweepShared {
     using T4 = typename Prec<T>::T4;
     static constexpr int P = kGroup / M;
-    T4 st_old[M][P];         // partner slice: position (old position for the band)
-    T4 st_new[M][P];         // partner slice: trial position (band / own group)
+    using SB = typename SliceBits<P>::type;
+    // per compute wave: staging of the current partner slice {x, y, z, q}
+    T4 st_old[M][P];
+    T4 st_new[M][P];
     T st_half[M][P];
-    double part_s[M][kGroup];        // per-wave partial sums
-    uint64_t part_ov[M];             // per-wave overlap ballots
-    uint32_t part_ovo[M][kGroup];    // own group: overlap with old positions (slice bits)
-    uint32_t part_ovt[M][kGroup];    // own group: overlap with trial positions (slice bits)
-    T c_own[kGroup][kGroup];         // own group corrections [partner j][mover i]
+    // hand-off from the compute waves to the chain wave (one target at a time)
+    double part_s[M][kGroup];   // partial sums over each wave's partners
+    uint64_t part_ov[M];        // overlap ballots over final partners
+    SB ovo_own[M][kGroup];      // own group, j < i: overlap with j's old position
+    SB ovt_own[M][kGroup];      //                   overlap with j's trial position
+    SB ovo_b0[M][kGroup];       // group g-1: overlap with old / trial position
+    SB ovt_b0[M][kGroup];
+    // corrections, one padded row per mover i (16-byte reads of 4 partners
+    // are free of bank conflicts)
+    static constexpr int CS = kGroup + (sizeof(T) == 4 ? 4 : 2);
+    T c_own[kGroup][CS];        // own group [mover i][partner j]
+    T c_b0[kGroup][CS];         // group g-1 [mover i][partner j]
+    int ready;                  // compute waves done filling the hand-off for the current target
+    int consumed;               // local target index + 1 the chain wave last released
 };
+
+// Bounded LDS wait used between the compute waves and the chain wave.
+__device__ __forceinline__ void wait_lds_at_least(int* flag, int want, const Ctl& ctl) {
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < want) {
+        const uint64_t t0 = wall_clock64();
+        for (;;) {
+            __builtin_amdgcn_s_sleep(1);
+            if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= want) break;
+            if (abort_raised(ctl)) break;
+            if (wall_clock64() - t0 > ctl.timeout_ticks) {
+                raise_timeout(ctl);
+                break;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// sum_j [bit j of mask] row[j] over the 64 partners, branch free: the row is
+// read with 16-byte loads and each value is ANDed with an all-ones or
+// all-zeros word built from the (wave-uniform) mask bit.  Fixed order, four
+// independent accumulators: deterministic.
+__device__ __forceinline__ float masked_pick(float v, uint64_t mask, int j) {
+    const uint32_t keep = 0u - (uint32_t)((mask >> j) & 1ull);
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) & keep);
+}
+__device__ __forceinline__ double masked_pick(double v, uint64_t mask, int j) {
+    const uint64_t keep = 0ull - ((mask >> j) & 1ull);
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & keep);
+}
+
+template <typename T>
+__device__ __forceinline__ T masked_row_sum(const T* __restrict__ row, uint64_t mask) {
+    constexpr int V = 16 / (int)sizeof(T);  // values per 16-byte read
+    typedef T VT __attribute__((ext_vector_type(V)));
+    T a[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kGroup; j += V) {
+        const VT v = *reinterpret_cast<const VT*>(row + j);
+#pragma unroll
+        for (int k = 0; k < V; ++k) a[(j + k) & 3] += masked_pick(v[k], mask, j + k);
+    }
+    return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+// The sequential part of target group g, run by wave 0 after its own share
+// of the pair terms: combine the waves' hand-off, wait for group g-1's accept
+// mask, decide the group by fixed-point iteration and publish.
+template <typename T, int M>
+__device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDesc& cd,
+                                           __amdgpu_buffer_rsrc_t pos_r, __amdgpu_buffer_rsrc_t rec_r,
+                                           const T* __restrict__ charge, int64_t g_begin, int64_t g, int t,
+                                           T xi, T yi, T zi, T txi, T tyi, T tzi, uint32_t w3,
+                                           const Ctl& ctl, unsigned long long& c_moves,
+                                           unsigned long long& c_acc, unsigned long long& c_wall,
+                                           unsigned long long& c_ov, unsigned long long& c_iters)
+{
+    using IO = PosIO<T>;
+    constexpr int P = kGroup / M;
+    const int lane = threadIdx.x & 63;
+    const int n = cd.n, nb = cd.nb, band = cd.band;
+    const int npad = nb * kGroup;
+    const int64_t s = g / nb;
+    const int b = (int)(g - s * nb);
+    const int ion = b * kGroup + lane;
+    const bool valid = ion < n;
+    const double qd = (double)charge[ion];
+    bool wall;
+    {
+        const double a = cd.wall_a[ion];
+        const double X = (double)txi, Y = (double)tyi, Z = (double)tzi;
+        const double r2 = X * X + Y * Y + Z * Z;
+        wall = r2 > a * a;
+    }
+    // Metropolis threshold: u3 < exp(-dE) is evaluated as dE < -log(u3), which
+    // is computed before the critical wait (the two forms can only disagree
+    // within rounding of the threshold itself; dE <= 0 always accepts)
+    const double thr = -log(accept_uniform(w3));
+
+#ifdef MC_TIMELINE
+    // diagnostic build only: per-group wall-clock stamps in the dE trace buffer
+    uint64_t tl0 = wall_clock64(), tl1 = 0, tl2 = 0;
+#endif
+    // the waves' partial sums
+    wait_lds_at_least(&sh.ready, M, ctl);
+#ifdef MC_TIMELINE
+    tl1 = wall_clock64();
+#endif
+    double St = 0.0;
+    uint64_t ovo = 0, ovt = 0, ovo0 = 0, ovt0 = 0;
+    bool ovb = false;
+#pragma unroll
+    for (int w = 0; w < M; ++w) {
+        St += sh.part_s[w][lane];
+        ovb |= ((sh.part_ov[w] >> lane) & 1ull) != 0;
+        ovo |= (uint64_t)sh.ovo_own[w][lane] << (w * P);
+        ovt |= (uint64_t)sh.ovt_own[w][lane] << (w * P);
+        ovo0 |= (uint64_t)sh.ovo_b0[w][lane] << (w * P);
+        ovt0 |= (uint64_t)sh.ovt_b0[w][lane] << (w * P);
+    }
+
+    // ---- the critical wait: group g-1's accept mask (with no band the waves
+    // already summed group g-1 as a decided group).  From here to the
+    // publication this wave is the chain's critical path: raise its issue
+    // priority over the compute waves sharing its SIMD.
+    __builtin_amdgcn_s_setprio(3);
+    if (band >= 1) {
+        const GroupRec r = wait_rec(rec_r, g - 1, ctl);
+#ifdef MC_TIMELINE
+        tl2 = wall_clock64();
+#endif
+        St += (double)masked_row_sum<T>(sh.c_b0[lane], r.acc);
+        ovb |= ((r.acc & ovt0) | (~r.acc & ovo0)) != 0;
+    }
+
+    // ---- sequential decisions inside the group by fixed-point iteration
+    const double lq = cd.lB * qd;
+    const bool can = valid && !wall && !ovb;
+    uint64_t acc = 0;
+    double dE = lq * St;
+    bool dec = can && (dE <= 0.0 || dE < thr);
+    int it = 1;
+    {
+        uint64_t nacc = __ballot(dec);
+        while (nacc != acc && it <= kGroup + 1) {
+            acc = nacc;
+            const T own = masked_row_sum<T>(sh.c_own[lane], acc);
+            const bool ovown = ((acc & ovt) | (~acc & ovo)) != 0;
+            dE = lq * (St + (double)own);
+            dec = can && !ovown && (dE <= 0.0 || dE < thr);
+            nacc = __ballot(dec);
+            ++it;
+        }
+        acc = nacc;
+    }
+    const uint64_t m_ov = __ballot(valid && !wall && (ovb || ((acc & ovt) | (~acc & ovo)) != 0));
+
+    // ---- release the hand-off buffer
+    if (lane == 0) {
+        __hip_atomic_store(&sh.ready, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __hip_atomic_store(&sh.consumed, t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+
+    // ---- publish the decisions at once; the positions follow
+    if (lane == 0) {
+        GroupRec r;
+        r.tag = (uint32_t)(g + 1);
+        r.spare = 0;
+        r.acc = acc;
+        store_rec(rec_r, (uint32_t)(g & (kRing - 1)), r);
+    }
+    if (dec)
+        IO::store(pos_r, (uint32_t)((s & 1) * npad + ion), txi, tyi, tzi, (uint32_t)s);
+    else
+        IO::store(pos_r, (uint32_t)((s & 1) * npad + ion), xi, yi, zi, (uint32_t)s);
+    __builtin_amdgcn_s_setprio(0);
+#ifdef MC_TIMELINE
+    if (lane == 0 && 4 * (g + 1) <= cd.trace_cap) {
+        uint64_t* tl = (uint64_t*)cd.trace_de + 4 * g;
+        tl[0] = tl0;
+        tl[1] = tl1;
+        tl[2] = tl2;
+        tl[3] = wall_clock64();
+    }
+#endif
+
+    const double de_group = __shfl(wave_sum(dec ? dE : 0.0), 0, 64);
+#ifndef MC_TIMELINE
+    if (valid) {
+#else
+    if (false) {
+#endif
+        const int64_t mv = s * (int64_t)n + ion;
+        if (mv < cd.trace_cap) {
+            cd.trace_acc[mv] = (uint8_t)dec;
+            cd.trace_de[mv] = dE;
+        }
+    }
+    if (lane == 0) cd.de_group[g - g_begin] = de_group;
+    const uint64_t m_wall = __ballot(valid && wall);
+    const uint64_t m_valid = __ballot(valid);
+    c_moves += __popcll(m_valid);
+    c_acc += __popcll(acc);
+    c_wall += __popcll(m_wall);
+    c_ov += __popcll(m_ov);
+    c_iters += it;
+}
+
+// Occupancy asked of the compiler (waves per SIMD): two workgroups per CU.
+template <typename T, int M>
+constexpr int kWavesPerEU = sizeof(T) == 4 ? (M == 8 ? 4 : 2) : 1;
 
 template <typename T, int M, bool UNIFORM_SIGMA>
 __global__ void __launch_bounds__(64 * M)
+__attribute__((amdgpu_waves_per_eu(kWavesPerEU<T, M>)))
 sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ wg_chain,
              uint32_t s0, int32_t n_sweeps, Ctl ctl)
 {
     using T4 = typename Prec<T>::T4;
+    using IO = PosIO<T>;
     constexpr int P = kGroup / M;
+    using SB = typename SliceBits<P>::type;
     __shared__ SweepShared<T, M> sh;
 
     const int lane = threadIdx.x & 63;
@@ -89,110 +388,58 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
     const ChainDesc& cd = chains[wg_chain[blockIdx.x]];
     const int k_wg = (int)blockIdx.x - cd.wg_first;
 
-    const int n = cd.n, nb = cd.nb, band = cd.band;
+    const int nb = cd.nb, band = cd.band;
     const int npad = nb * kGroup;
-    T4* __restrict__ pos = (T4*)cd.pos;
+    const __amdgpu_buffer_rsrc_t pos_r = make_rsrc(cd.pos, (uint32_t)(2u * npad * IO::kBytes));
+    const __amdgpu_buffer_rsrc_t rec_r = make_rsrc(cd.rec, (uint32_t)(kRing * sizeof(GroupRec)));
+    const T* __restrict__ charge = (const T*)cd.charge;
     const T* __restrict__ half = (const T*)cd.half;
     const T D = (T)cd.D;
-    const double lB = cd.lB;
     const T hu = (T)cd.half_uniform;
     const int64_t g_begin = (int64_t)s0 * nb;
     const int64_t g_end = g_begin + (int64_t)n_sweeps * nb;
-    int64_t known = -1;  // largest front value this wave has observed
 
-    for (int64_t g = g_begin + k_wg; g < g_end; g += cd.wg_count) {
-        const int64_t s = g / nb;
-        const int b = (int)(g - s * nb);
-        const int ion = b * kGroup + lane;
-        const bool valid = ion < n;
+    if (threadIdx.x == 0) {
+        sh.ready = 0;
+        sh.consumed = 0;
+    }
+    __syncthreads();
 
-        // ---- the movers: old position (result of the group's previous trial) and trial
-        wait_front(cd.front, g - nb + 1, known, ctl);
-        const T4 xo = pos[(size_t)((s - 1) & 1) * npad + ion];
-        const uint4 wd = move_words(cd.seed, cd.chain_id, (uint32_t)s, (uint32_t)ion);
-        const T xi = xo.x, yi = xo.y, zi = xo.z, qi = xo.w;
-        const T txi = trial_coord(xi, wd.x, D), tyi = trial_coord(yi, wd.y, D),
-                tzi = trial_coord(zi, wd.z, D);
-        const T hi = UNIFORM_SIGMA ? hu : half[ion];
-        bool wall;
-        {
-            const double a = cd.wall_a[ion];
-            const double X = (double)txi, Y = (double)tyi, Z = (double)tzi;
-            const double r2 = X * X + Y * Y + Z * Z;
-            wall = r2 > a * a;
-        }
-        const double u3 = accept_uniform(wd.w);
+    unsigned long long c_moves = 0, c_acc = 0, c_wall = 0, c_ov = 0, c_iters = 0;
+    {
+        int t = 0;
+        for (int64_t g = g_begin + k_wg; g < g_end; g += cd.wg_count, ++t) {
+            const int64_t s = g / nb;
+            const int b = (int)(g - s * nb);
+            const int ion = b * kGroup + lane;
 
-        double S = 0.0;     // sum_j q_j (1/|x~_i - x_j| - 1/|x_i - x_j|)
-        bool ov = false;    // overlap with a partner whose position is final
+            // the movers: old position = result of the group's previous trial
+            const auto xr = IO::load_valid(pos_r, (uint32_t)(((s - 1) & 1) * npad + ion), (uint32_t)(s - 1),
+                                           true, ctl);
+            const T xi = xr.x, yi = xr.y, zi = xr.z, qi = charge[ion];
+            const uint4 wd = move_words(cd.seed, cd.chain_id, (uint32_t)s, (uint32_t)ion);
+            const T txi = trial_coord(xi, wd.x, D), tyi = trial_coord(yi, wd.y, D),
+                    tzi = trial_coord(zi, wd.z, D);
+            const T hi = UNIFORM_SIGMA ? hu : half[ion];
 
-        // ---- own group: both outcomes of every partner j != i
-        T c_own[P];
-        uint32_t ovo_own = 0, ovt_own = 0;
-        {
-            if (lane >= wave * P && lane < wave * P + P) {
-                const int m = lane - wave * P;
-                sh.st_old[wave][m] = xo;
-                sh.st_new[wave][m] = mk4<T>(txi, tyi, tzi, qi);
-                sh.st_half[wave][m] = hi;
-            }
-            wave_lds_sync();
-            T sf = 0;
-#pragma unroll
-            for (int m = 0; m < P; ++m) {
-                const int j = wave * P + m;
-                const T4 po = sh.st_old[wave][m];
-                const T4 pt = sh.st_new[wave][m];
-                const T hj = UNIFORM_SIGMA ? hu : sh.st_half[wave][m];
-                const T s_ij = hi + hj;
-                const T d2o = Prec<T>::norm2(po.x - xi, po.y - yi, po.z - zi);
-                const T d2ot = Prec<T>::norm2(po.x - txi, po.y - tyi, po.z - tzi);
-                const T d2t = Prec<T>::norm2(pt.x - xi, pt.y - yi, pt.z - zi);
-                const T d2tt = Prec<T>::norm2(pt.x - txi, pt.y - tyi, pt.z - tzi);
-                const T o = po.w * (Prec<T>::rinv(d2ot) - Prec<T>::rinv(d2o));
-                const T t = pt.w * (Prec<T>::rinv(d2tt) - Prec<T>::rinv(d2t));
-                const bool oo = d2ot < s_ij * s_ij, ot = d2tt < s_ij * s_ij;
-                if (j > lane) {
-                    sf += o;
-                    ov |= oo;
-                    c_own[m] = 0;
-                } else if (j < lane) {
-                    sf += o;
-                    c_own[m] = t - o;
-                    ovo_own |= (uint32_t)oo << m;
-                    ovt_own |= (uint32_t)ot << m;
-                } else {
-                    c_own[m] = 0;
-                }
-            }
-            S += (double)sf;
-        }
+            double S = 0.0;     // sum_j q_j (1/|x~_i - x_j| - 1/|x_i - x_j|)
+            bool ov = false;    // overlap with a partner whose position is final
 
-        // ---- band groups g-1..g-band: both outcomes, evaluated ahead of their decisions
-        T c_band[kMaxBand][P];
-        uint32_t ovo_band[kMaxBand], ovt_band[kMaxBand];
-#pragma unroll
-        for (int kb = 0; kb < kMaxBand; ++kb) {
-            ovo_band[kb] = 0;
-            ovt_band[kb] = 0;
-            if (kb < band) {
-                const int64_t gp = g - 1 - kb;
-                const int64_t sp = floor_div(gp, nb);
-                const int bp = (int)(gp - sp * nb);
-                // old position of j = result of its trial one sweep before (front >= g-nb+1 covers it)
-                if (lane < P) {
-                    const int j = bp * kGroup + wave * P + lane;
-                    const T4 po = pos[(size_t)((sp - 1) & 1) * npad + j];
-                    const uint4 wj = move_words(cd.seed, cd.chain_id, (uint32_t)sp, (uint32_t)j);
-                    sh.st_old[wave][lane] = po;
-                    sh.st_new[wave][lane] = mk4<T>(trial_coord(po.x, wj.x, D), trial_coord(po.y, wj.y, D),
-                                                    trial_coord(po.z, wj.z, D), po.w);
-                    if (!UNIFORM_SIGMA) sh.st_half[wave][lane] = half[j];
+            // ---- own group: both outcomes of every partner j != i
+            T c_own[P];
+            SB ovo_own = 0, ovt_own = 0;
+            {
+                if (lane >= wave * P && lane < wave * P + P) {
+                    const int m = lane - wave * P;
+                    sh.st_old[wave][m] = mk4<T>(xi, yi, zi, qi);
+                    sh.st_new[wave][m] = mk4<T>(txi, tyi, tzi, qi);
+                    sh.st_half[wave][m] = hi;
                 }
                 wave_lds_sync();
                 T sf = 0;
 #pragma unroll
                 for (int m = 0; m < P; ++m) {
+                    const int j = wave * P + m;
                     const T4 po = sh.st_old[wave][m];
                     const T4 pt = sh.st_new[wave][m];
                     const T hj = UNIFORM_SIGMA ? hu : sh.st_half[wave][m];
@@ -202,148 +449,199 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
                     const T d2t = Prec<T>::norm2(pt.x - xi, pt.y - yi, pt.z - zi);
                     const T d2tt = Prec<T>::norm2(pt.x - txi, pt.y - tyi, pt.z - tzi);
                     const T o = po.w * (Prec<T>::rinv(d2ot) - Prec<T>::rinv(d2o));
-                    const T t = pt.w * (Prec<T>::rinv(d2tt) - Prec<T>::rinv(d2t));
-                    sf += o;
-                    c_band[kb][m] = t - o;
-                    ovo_band[kb] |= (uint32_t)(d2ot < s_ij * s_ij) << m;
-                    ovt_band[kb] |= (uint32_t)(d2tt < s_ij * s_ij) << m;
+                    const T tt = pt.w * (Prec<T>::rinv(d2tt) - Prec<T>::rinv(d2t));
+                    const bool oo = d2ot < s_ij * s_ij, ot = d2tt < s_ij * s_ij;
+                    if (j > lane) {
+                        sf += o;
+                        ov |= oo;
+                        c_own[m] = 0;
+                    } else if (j < lane) {
+                        sf += o;
+                        c_own[m] = tt - o;
+                        ovo_own |= (SB)((SB)oo << m);
+                        ovt_own |= (SB)((SB)ot << m);
+                    } else {
+                        c_own[m] = 0;
+                    }
                 }
                 S += (double)sf;
                 wave_lds_sync();
             }
-        }
 
-        // ---- decided partner groups g-nb+1 .. g-band-1, in stream order
-        int64_t sp = (b + 1 < nb) ? s - 1 : s;   // sweep and group of g-nb+1
-        int bp = (b + 1 < nb) ? b + 1 : 0;
-        for (int64_t gp = g - nb + 1; gp <= g - band - 1; ++gp) {
-            wait_front(cd.front, gp + 1, known, ctl);
-            if (lane < P) {
-                const int j = bp * kGroup + wave * P + lane;
-                sh.st_old[wave][lane] = pos[(size_t)(sp & 1) * npad + j];
-                if (!UNIFORM_SIGMA) sh.st_half[wave][lane] = half[j];
+            // ---- band groups g-1..g-band: both outcomes, evaluated ahead of their decisions
+            T c_band[kMaxBand][P];
+            SB ovo_band[kMaxBand], ovt_band[kMaxBand];
+#pragma unroll
+            for (int kb = 0; kb < kMaxBand; ++kb) {
+                ovo_band[kb] = 0;
+                ovt_band[kb] = 0;
+#pragma unroll
+                for (int m = 0; m < P; ++m) c_band[kb][m] = 0;
+                if (kb < band) {
+                    const int64_t gp = g - 1 - kb;
+                    const int64_t sp = floor_div(gp, nb);
+                    const int bp = (int)(gp - sp * nb);
+                    // old position of j = result of its trial one sweep before
+                    const int j = bp * kGroup + wave * P + (lane < P ? lane : 0);
+                    const auto pr = IO::load_valid(pos_r, (uint32_t)(((sp - 1) & 1) * npad + j),
+                                                   (uint32_t)(sp - 1), lane < P, ctl);
+                    if (lane < P) {
+                        const T qj = charge[j];
+                        const uint4 wj = move_words(cd.seed, cd.chain_id, (uint32_t)sp, (uint32_t)j);
+                        sh.st_old[wave][lane] = mk4<T>(pr.x, pr.y, pr.z, qj);
+                        sh.st_new[wave][lane] = mk4<T>(trial_coord((T)pr.x, wj.x, D), trial_coord((T)pr.y, wj.y, D),
+                                                        trial_coord((T)pr.z, wj.z, D), qj);
+                        if (!UNIFORM_SIGMA) sh.st_half[wave][lane] = half[j];
+                    }
+                    wave_lds_sync();
+                    T sf = 0;
+#pragma unroll
+                    for (int m = 0; m < P; ++m) {
+                        const T4 po = sh.st_old[wave][m];
+                        const T4 pt = sh.st_new[wave][m];
+                        const T hj = UNIFORM_SIGMA ? hu : sh.st_half[wave][m];
+                        const T s_ij = hi + hj;
+                        const T d2o = Prec<T>::norm2(po.x - xi, po.y - yi, po.z - zi);
+                        const T d2ot = Prec<T>::norm2(po.x - txi, po.y - tyi, po.z - tzi);
+                        const T d2t = Prec<T>::norm2(pt.x - xi, pt.y - yi, pt.z - zi);
+                        const T d2tt = Prec<T>::norm2(pt.x - txi, pt.y - tyi, pt.z - tzi);
+                        const T o = po.w * (Prec<T>::rinv(d2ot) - Prec<T>::rinv(d2o));
+                        const T tt = pt.w * (Prec<T>::rinv(d2tt) - Prec<T>::rinv(d2t));
+                        sf += o;
+                        c_band[kb][m] = tt - o;
+                        ovo_band[kb] |= (SB)((SB)(d2ot < s_ij * s_ij) << m);
+                        ovt_band[kb] |= (SB)((SB)(d2tt < s_ij * s_ij) << m);
+                    }
+                    S += (double)sf;
+                    wave_lds_sync();
+                }
             }
-            wave_lds_sync();
-            T sf = 0;
+
+            // ---- decided partner groups g-nb+1 .. g-band-1, in stream order.  The next
+            // tile is loaded speculatively while this one is computed (float path); a
+            // record whose version is not the expected one yet is loaded again.
+            {
+                const int64_t g_last = g - band - 1;
+                int64_t sp = (b + 1 < nb) ? s - 1 : s;   // sweep and group of g-nb+1
+                int bp = (b + 1 < nb) ? b + 1 : 0;
+                const int jl = wave * P + (lane < P ? lane : 0);
+                typename IO::Rec nxt{};
+                bool have_next = false;
+                for (int64_t gp = g - nb + 1; gp <= g_last; ++gp) {
+                    const int j = bp * kGroup + jl;
+                    typename IO::Rec cur;
+                    if (have_next && __ballot(lane < P && nxt.ver != (uint32_t)sp) == 0ull)
+                        cur = nxt;
+                    else
+                        cur = IO::load_valid(pos_r, (uint32_t)((sp & 1) * npad + j), (uint32_t)sp, lane < P, ctl);
+                    if (lane < P) {
+                        sh.st_old[wave][lane] = mk4<T>(cur.x, cur.y, cur.z, charge[j]);
+                        if (!UNIFORM_SIGMA) sh.st_half[wave][lane] = half[j];
+                    }
+                    wave_lds_sync();
+                    int bn = bp + 1;
+                    int64_t sn = sp;
+                    if (bn == nb) {
+                        bn = 0;
+                        ++sn;
+                    }
+                    have_next = false;
+                    if constexpr (sizeof(T) == 4) {
+                        if (gp + 1 <= g_last) {
+                            if (lane < P) nxt = IO::load(pos_r, (uint32_t)((sn & 1) * npad + bn * kGroup + jl));
+                            have_next = true;
+                        }
+                    }
+                    T sf = 0;
+#pragma unroll
+                    for (int m = 0; m < P; ++m) {
+                        const T4 p = sh.st_old[wave][m];
+                        const T hj = UNIFORM_SIGMA ? hu : sh.st_half[wave][m];
+                        const T s_ij = hi + hj;
+                        const T d2 = Prec<T>::norm2(p.x - xi, p.y - yi, p.z - zi);
+                        const T d2t = Prec<T>::norm2(p.x - txi, p.y - tyi, p.z - tzi);
+                        sf = Prec<T>::fma(p.w, Prec<T>::rinv(d2t) - Prec<T>::rinv(d2), sf);
+                        ov |= d2t < s_ij * s_ij;
+                    }
+                    S += (double)sf;
+                    wave_lds_sync();
+                    bp = bn;
+                    sp = sn;
+                }
+            }
+
+            // ---- band groups g-band..g-2 are decided well before g: apply them here
+#pragma unroll
+            for (int kb = kMaxBand - 1; kb >= 1; --kb) {
+                if (kb < band) {
+                    const GroupRec r = wait_rec(rec_r, g - 1 - kb, ctl);
+                    const uint32_t a = (uint32_t)(r.acc >> (wave * P)) & (uint32_t)((1ull << P) - 1);
+                    T cf = 0;
+#pragma unroll
+                    for (int m = 0; m < P; ++m)
+                        if ((a >> m) & 1u) cf += c_band[kb][m];
+                    S += (double)cf;
+                    ov |= ((((SB)a & ovt_band[kb]) | ((SB)~a & ovo_band[kb])) != 0);
+                }
+            }
+
+            // ---- hand off to the chain wave once it has released the previous target
+            wait_lds_at_least(&sh.consumed, t, ctl);
+            sh.part_s[wave][lane] = S;
+            {
+                const uint64_t ob = __ballot(ov);
+                if (lane == 0) sh.part_ov[wave] = ob;
+            }
+            sh.ovo_own[wave][lane] = ovo_own;
+            sh.ovt_own[wave][lane] = ovt_own;
+            sh.ovo_b0[wave][lane] = ovo_band[0];
+            sh.ovt_b0[wave][lane] = ovt_band[0];
 #pragma unroll
             for (int m = 0; m < P; ++m) {
-                const T4 p = sh.st_old[wave][m];
-                const T hj = UNIFORM_SIGMA ? hu : sh.st_half[wave][m];
-                const T s_ij = hi + hj;
-                const T d2 = Prec<T>::norm2(p.x - xi, p.y - yi, p.z - zi);
-                const T d2t = Prec<T>::norm2(p.x - txi, p.y - tyi, p.z - tzi);
-                sf = Prec<T>::fma(p.w, Prec<T>::rinv(d2t) - Prec<T>::rinv(d2), sf);
-                ov |= d2t < s_ij * s_ij;
+                sh.c_own[lane][wave * P + m] = c_own[m];
+                sh.c_b0[lane][wave * P + m] = c_band[0][m];
             }
-            S += (double)sf;
-            wave_lds_sync();
-            if (++bp == nb) {
-                bp = 0;
-                ++sp;
-            }
-        }
-
-        // ---- apply the band groups' decisions as they arrive (oldest first)
-        double e_prev = 0.0;
-#pragma unroll
-        for (int kb = kMaxBand - 1; kb >= 0; --kb) {
-            if (kb < band) {
-                const int64_t gp = g - 1 - kb;
-                wait_front(cd.front, gp + 1, known, ctl);
-                const uint64_t acc = cd.rec[(size_t)(gp & (kRing - 1))].acc;
-                const uint32_t a = (uint32_t)(acc >> (wave * P)) & (uint32_t)((1ull << P) - 1);
-                T cf = 0;
-#pragma unroll
-                for (int m = 0; m < P; ++m)
-                    if ((a >> m) & 1u) cf += c_band[kb][m];
-                S += (double)cf;
-                ov |= (((a & ovt_band[kb]) | (~a & ovo_band[kb])) != 0u);
-            }
-        }
-
-        // ---- combine the waves
-        sh.part_s[wave][lane] = S;
-        {
-            const uint64_t ob = __ballot(ov);
-            if (lane == 0) sh.part_ov[wave] = ob;
-        }
-        sh.part_ovo[wave][lane] = ovo_own;
-        sh.part_ovt[wave][lane] = ovt_own;
-#pragma unroll
-        for (int m = 0; m < P; ++m) sh.c_own[wave * P + m][lane] = c_own[m];
-        __syncthreads();
-
-        if (wave == 0) {
-            double St = 0.0;
-            uint64_t ovo = 0, ovt = 0;
-            bool ovb = false;
-#pragma unroll
-            for (int w = 0; w < M; ++w) {
-                St += sh.part_s[w][lane];
-                ovb |= ((sh.part_ov[w] >> lane) & 1ull) != 0;
-                ovo |= (uint64_t)sh.part_ovo[w][lane] << (w * P);
-                ovt |= (uint64_t)sh.part_ovt[w][lane] << (w * P);
-            }
-            wait_front(cd.front, g, known, ctl);  // group g-1 decided: running energy
-            e_prev = cd.rec[(size_t)((g - 1) & (kRing - 1))].e_run;
-
-            // Sequential decisions inside the group by fixed-point iteration.
-            const double lq = lB * (double)qi;
-            uint64_t acc = 0;
-            double dE = 0.0;
-            bool dec = false;
-            int it = 0;
-            for (;;) {
-                T own = 0;
-                uint64_t bits = acc;
-                while (bits) {
-                    const int j = __builtin_ctzll(bits);
-                    bits &= bits - 1;
-                    own += sh.c_own[j][lane];
-                }
-                const bool ovown = ((acc & ovt) | (~acc & ovo)) != 0;
-                dE = lq * (St + (double)own);
-                dec = valid && !wall && !ovb && !ovown && (dE <= 0.0 || u3 < exp(-dE));
-                const uint64_t nacc = __ballot(dec);
-                ++it;
-                if (nacc == acc || it > kGroup + 1) { acc = nacc; break; }
-                acc = nacc;
-            }
-
-            // in-place update (double buffered by sweep parity)
-            pos[(size_t)(s & 1) * npad + ion] = dec ? mk4<T>(txi, tyi, tzi, qi) : xo;
-            const double de_acc = __shfl(wave_sum(dec ? dE : 0.0), 0, 64);
-            const double e_new = e_prev + de_acc;
-            if (valid) {
-                const int64_t mv = s * (int64_t)n + ion;
-                if (mv < cd.trace_cap) {
-                    cd.trace_acc[mv] = (uint8_t)dec;
-                    cd.trace_de[mv] = dE;
-                }
-            }
-            const uint64_t m_wall = __ballot(valid && wall);
-            const uint64_t m_ov = __ballot(valid && !wall && (ovb || ((acc & ovt) | (~acc & ovo)) != 0));
-            const uint64_t m_valid = __ballot(valid);
-            if (lane == 0) {
-                atomicAdd(&cd.stats[0], (unsigned long long)__popcll(m_valid));
-                atomicAdd(&cd.stats[1], (unsigned long long)__popcll(acc));
-                atomicAdd(&cd.stats[2], (unsigned long long)__popcll(m_wall));
-                atomicAdd(&cd.stats[3], (unsigned long long)__popcll(m_ov));
-                atomicAdd(&cd.stats[4], (unsigned long long)(__popcll(m_valid) - __popcll(acc) -
-                                                             __popcll(m_wall) - __popcll(m_ov)));
-                atomicAdd(&cd.stats[5], (unsigned long long)it);
-                if (b == nb - 1 && s < cd.e_capacity) cd.e_series[s] = e_new;
-                GroupRec& r = cd.rec[(size_t)(g & (kRing - 1))];
-                r.acc = acc;
-                r.e_run = e_new;
-                r.tag = g + 1;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             if (lane == 0)
-                __hip_atomic_store(cd.front, (uint64_t)(g + 1), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&sh.ready, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+
+            // ---- wave 0 finishes the group: decisions and publication
+            if (wave == 0)
+                chain_step<T, M>(sh, cd, pos_r, rec_r, charge, g_begin, g, t, xi, yi, zi, txi, tyi, tzi,
+                                 wd.w, ctl, c_moves, c_acc, c_wall, c_ov, c_iters);
         }
-        __syncthreads();
+    }
+    if (wave == 0 && lane == 0 && c_moves) {
+        atomicAdd(&cd.stats[0], c_moves);
+        atomicAdd(&cd.stats[1], c_acc);
+        atomicAdd(&cd.stats[2], c_wall);
+        atomicAdd(&cd.stats[3], c_ov);
+        atomicAdd(&cd.stats[4], c_moves - c_acc - c_wall - c_ov);
+        atomicAdd(&cd.stats[5], c_iters);
+    }
+}
+
+// Running energy after each sweep of a launch: per-sweep totals of the group
+// energy changes (each summed in group order), then a serial prefix from the
+// previous running energy.  Deterministic.
+__global__ void __launch_bounds__(256)
+energy_scan_kernel(const double* __restrict__ de_group, int nb, int32_t n_sweeps, int64_t s0,
+                   double* __restrict__ sweep_tot, double* __restrict__ e_state,
+                   double* __restrict__ e_series, int64_t e_capacity)
+{
+    for (int s = threadIdx.x; s < n_sweeps; s += blockDim.x) {
+        double t = 0.0;
+        for (int b = 0; b < nb; ++b) t += de_group[(int64_t)s * nb + b];
+        sweep_tot[s] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double e = *e_state;
+        for (int s = 0; s < n_sweeps; ++s) {
+            e += sweep_tot[s];
+            if (s0 + s < e_capacity) e_series[s0 + s] = e;
+        }
+        *e_state = e;
     }
 }
 
