@@ -188,6 +188,8 @@ typedef struct mc_stats {
     int64_t rejected_overlap;/* rejected by the hard-core indicator (not wall)     */
     int64_t rejected_metropolis; /* rejected by the Metropolis test                */
     int64_t fixpoint_iterations; /* in-group decision iterations (diagnostic)      */
+    int64_t early_groups;    /* groups decided from bounds before their predecessor's
+                                decisions were known (diagnostic)                  */
     int64_t resums;          /* double-precision energy re-sums done               */
     double last_drift;       /* running minus re-summed energy at the last re-sum  */
     double max_abs_drift;    /* largest |drift| over all re-sums                   */

@@ -11,7 +11,7 @@
 namespace mcdev {
 
 constexpr int kGroup = 64;   // movers per group = lanes of one wavefront
-constexpr int kRing = 64;    // group records kept per chain (must exceed the band)
+constexpr int kRing = 1024;  // group records kept per chain
 constexpr int kMaxBand = 2;  // largest look-ahead band, in groups
 
 // Per-group record published by the workgroup that decided the group; one
@@ -166,17 +166,26 @@ __device__ __forceinline__ void raise_timeout(const Ctl& ctl) {
 }
 
 // Waits for the record of group gp and returns it.  A record only carries the
-// group's accept mask (positions carry their own version tags).  Callers only
-// ask for groups still in the ring (the band), so the slot holds exactly
-// group gp once its tag matches.
+// group's accept mask (positions carry their own version tags).  Readers are
+// at most a few groups behind the newest publication, far fewer than the
+// ring holds; a slot found already reused raises MC_E_STATE.
 __device__ __forceinline__ GroupRec wait_rec(__amdgpu_buffer_rsrc_t rr, int64_t gp, const Ctl& ctl) {
     const uint32_t slot = (uint32_t)(gp & (kRing - 1));
     const uint32_t want = (uint32_t)(gp + 1);
     const uint64_t t0 = wall_clock64();
     for (;;) {
         const GroupRec r = load_rec(rr, slot);
-        if ((int32_t)(r.tag - want) >= 0) {
+        const int32_t ahead = (int32_t)(r.tag - want);
+        if (ahead == 0) {
             compiler_fence();
+            return r;
+        }
+        if (ahead > 0) {
+            // the slot was reused before this reader got to it: report, never guess
+            int expected = 0;
+            __hip_atomic_compare_exchange_strong(ctl.abort, &expected, -8 /* MC_E_STATE */,
+                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
             return r;
         }
         if (abort_raised(ctl)) return r;

@@ -31,7 +31,7 @@ namespace {
 thread_local std::string g_create_error = "no error";
 
 // Stats slots written by the sweep kernel.
-enum { ST_MOVES = 0, ST_ACC, ST_WALL, ST_OVERLAP, ST_METRO, ST_ITERS, ST_N };
+enum { ST_MOVES = 0, ST_ACC, ST_WALL, ST_OVERLAP, ST_METRO, ST_ITERS, ST_EARLY, ST_N };
 
 struct DeviceInfo {
     int device = -1;
@@ -138,7 +138,7 @@ namespace {
 int fail(mc_handle* h, int code, const std::string& msg) {
     if (h) {
         h->err = msg;
-        if (code == MC_E_DEVICE || code == MC_E_TIMEOUT) h->failed = true;
+        if (code == MC_E_DEVICE || code == MC_E_TIMEOUT || (code == MC_E_STATE && !h->failed)) h->failed = true;
     } else {
         g_create_error = msg;
     }
@@ -190,8 +190,9 @@ int sync_check(mc_handle* h) {
     int ab = 0;
     HIPCHECK(h, hipMemcpy(&ab, h->abort_flag, sizeof(int), hipMemcpyDeviceToHost));
     if (ab != 0) {
-        return fail(h, ab == MC_E_TIMEOUT ? MC_E_TIMEOUT : MC_E_DEVICE,
+        return fail(h, ab == MC_E_TIMEOUT ? MC_E_TIMEOUT : ab == MC_E_STATE ? MC_E_STATE : MC_E_DEVICE,
                     ab == MC_E_TIMEOUT ? "a device-side wait timed out (chain state is invalid)"
+                    : ab == MC_E_STATE ? "a group record was reused before it was read (chain state is invalid)"
                                        : "device reported an error");
     }
     return MC_OK;
@@ -558,7 +559,7 @@ int mc_create(int32_t n, const double* charges, const double* diameters, const d
     }
     std::vector<GroupRec> hrec(kRing);
     for (int k = 0; k < kRing; ++k) {
-        const int64_t g = (int64_t)k - kRing;  // virtual groups -64..-1: decided, nothing accepted
+        const int64_t g = (int64_t)k - kRing;  // virtual groups -kRing..-1: decided, nothing accepted
         hrec[(size_t)(g & (kRing - 1))] = GroupRec{(uint32_t)(g + 1), 0u, 0ull};
     }
     auto up = [&](void* dst, const void* src, size_t bytes) {
@@ -807,6 +808,7 @@ int mc_get_stats(mc_handle* h, mc_stats* out) {
     out->rejected_overlap = (int64_t)st[ST_OVERLAP];
     out->rejected_metropolis = (int64_t)st[ST_METRO];
     out->fixpoint_iterations = (int64_t)st[ST_ITERS];
+    out->early_groups = (int64_t)st[ST_EARLY];
     out->resums = (int64_t)a.n_resum;
     out->last_drift = a.drift_last;
     out->max_abs_drift = a.drift_max;

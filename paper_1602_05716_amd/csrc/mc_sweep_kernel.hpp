@@ -59,7 +59,7 @@ struct ChainDesc {
     void* half;          // T[npad]: sigma_i / 2
     const double* wall_a;// double[npad]: R - sigma_i / 2
     GroupRec* rec;       // [kRing]
-    unsigned long long* stats;  // [8] counters, see mc_host
+    unsigned long long* stats;  // [7] counters: moves, accepted, wall, overlap, Metropolis rejections, iterations, early groups
     double* de_group;    // [launch groups] energy change of each group of the launch
     uint8_t* trace_acc;  // [trace_cap]
     double* trace_de;    // [trace_cap]
@@ -166,6 +166,8 @@ struct SweepShared {
     // hand-off from the compute waves to the chain wave (one target at a time)
     double part_s[M][kGroup];   // partial sums over each wave's partners
     uint64_t part_ov[M];        // overlap ballots over final partners
+    T part_pn[M][4][kGroup];    // per wave: sums of the positive / negative
+                                // corrections of group g-1 and of the own group
     SB ovo_own[M][kGroup];      // own group, j < i: overlap with j's old position
     SB ovt_own[M][kGroup];      //                   overlap with j's trial position
     SB ovo_b0[M][kGroup];       // group g-1: overlap with old / trial position
@@ -223,6 +225,27 @@ __device__ __forceinline__ T masked_row_sum(const T* __restrict__ row, uint64_t 
     return (a[0] + a[1]) + (a[2] + a[3]);
 }
 
+// Publishes group g: its accept mask in the group record, then the new
+// positions (trial position if accepted, old one otherwise), each tagged with
+// the sweep index.
+template <typename T>
+__device__ __forceinline__ void publish_group(__amdgpu_buffer_rsrc_t rec_r, __amdgpu_buffer_rsrc_t pos_r,
+                                              int64_t g, int64_t s, int npad, int ion, uint64_t acc,
+                                              bool dec, T xi, T yi, T zi, T txi, T tyi, T tzi) {
+    using IO = PosIO<T>;
+    if ((threadIdx.x & 63) == 0) {
+        GroupRec r;
+        r.tag = (uint32_t)(g + 1);
+        r.spare = 0;
+        r.acc = acc;
+        store_rec(rec_r, (uint32_t)(g & (kRing - 1)), r);
+    }
+    if (dec)
+        IO::store(pos_r, (uint32_t)((s & 1) * npad + ion), txi, tyi, tzi, (uint32_t)s);
+    else
+        IO::store(pos_r, (uint32_t)((s & 1) * npad + ion), xi, yi, zi, (uint32_t)s);
+}
+
 // The sequential part of target group g, run by wave 0 after its own share
 // of the pair terms: combine the waves' hand-off, wait for group g-1's accept
 // mask, decide the group by fixed-point iteration and publish.
@@ -233,9 +256,9 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
                                            T xi, T yi, T zi, T txi, T tyi, T tzi, uint32_t w3,
                                            const Ctl& ctl, unsigned long long& c_moves,
                                            unsigned long long& c_acc, unsigned long long& c_wall,
-                                           unsigned long long& c_ov, unsigned long long& c_iters)
+                                           unsigned long long& c_ov, unsigned long long& c_iters,
+                                           unsigned long long& c_early)
 {
-    using IO = PosIO<T>;
     constexpr int P = kGroup / M;
     const int lane = threadIdx.x & 63;
     const int n = cd.n, nb = cd.nb, band = cd.band;
@@ -259,7 +282,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
 
 #ifdef MC_TIMELINE
     // diagnostic build only: per-group wall-clock stamps in the dE trace buffer
-    uint64_t tl0 = wall_clock64(), tl1 = 0, tl2 = 0;
+    uint64_t tl0 = wall_clock64(), tl1 = 0, tl2 = 0, tl3 = 0;
 #endif
     // the waves' partial sums
     wait_lds_at_least(&sh.ready, M, ctl);
@@ -269,8 +292,13 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
     double St = 0.0;
     uint64_t ovo = 0, ovt = 0, ovo0 = 0, ovt0 = 0;
     bool ovb = false;
+    T bp = 0, bn = 0, op = 0, on = 0;
 #pragma unroll
     for (int w = 0; w < M; ++w) {
+        bp += sh.part_pn[w][0][lane];
+        bn += sh.part_pn[w][1][lane];
+        op += sh.part_pn[w][2][lane];
+        on += sh.part_pn[w][3][lane];
         St += sh.part_s[w][lane];
         ovb |= ((sh.part_ov[w] >> lane) & 1ull) != 0;
         ovo |= (uint64_t)sh.ovo_own[w][lane] << (w * P);
@@ -279,39 +307,81 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
         ovt0 |= (uint64_t)sh.ovt_b0[w][lane] << (w * P);
     }
 
-    // ---- the critical wait: group g-1's accept mask (with no band the waves
-    // already summed group g-1 as a decided group).  From here to the
-    // publication this wave is the chain's critical path: raise its issue
-    // priority over the compute waves sharing its SIMD.
+    // ---- decisions.  dE = lB q (St + corr_{g-1} + own) with corr_{g-1} and
+    // own unknown until group g-1's and this group's accept bits are known,
+    // but bounded by the sums of their negative and positive terms.  When the
+    // threshold lies outside every lane's interval (with a margin far larger
+    // than the rounding of these sums) and no hard-core overlap can flip, the
+    // group's decisions are certain and are published before group g-1's
+    // accept mask has even arrived; the exact dE follows.  Otherwise: wait
+    // for group g-1 and iterate the sequential rule to its fixed point.
     __builtin_amdgcn_s_setprio(3);
+    const double lq = cd.lB * qd;
+    const bool can = valid && !wall && !ovb;
+    uint64_t acc = 0;
+    double dE = 0.0;
+    bool dec = false;
+    int it = 0;
+    bool early = false;
+    {
+        const bool use_b0 = band >= 1;
+        const double lo = St + (use_b0 ? (double)bn : 0.0) + (double)on;
+        const double hi = St + (use_b0 ? (double)bp : 0.0) + (double)op;
+        const double e_lo = lq >= 0 ? lq * lo : lq * hi;
+        const double e_hi = lq >= 0 ? lq * hi : lq * lo;
+        const double span = (double)((use_b0 ? bp - bn : (T)0) + (op - on));
+        const double margin = fabs(lq) * (1e-4 * span + 1e-9 * (fabs(St) + 1.0)) + 1e-12;
+        const uint64_t ov_sure = use_b0 ? (ovo0 & ovt0) : 0ull;
+        const uint64_t ov_flip = (use_b0 ? (ovo0 ^ ovt0) : 0ull) | (ovo ^ ovt);
+        const bool reject_sure = !can || ov_sure != 0 || (ovo & ovt) != 0;
+        const bool accept_sure = !reject_sure && ov_flip == 0 && e_hi < thr - margin;
+        const bool sure = reject_sure || accept_sure || (ov_flip == 0 && e_lo >= thr + margin);
+        if (__ballot(!sure) == 0ull) {
+            early = true;
+            acc = __ballot(accept_sure);
+            dec = accept_sure;
+            publish_group<T>(rec_r, pos_r, g, s, npad, ion, acc, dec, xi, yi, zi, txi, tyi, tzi);
+#ifdef MC_TIMELINE
+            tl3 = wall_clock64();
+#endif
+        }
+    }
+    double corr = 0.0;
     if (band >= 1) {
         const GroupRec r = wait_rec(rec_r, g - 1, ctl);
 #ifdef MC_TIMELINE
         tl2 = wall_clock64();
 #endif
-        St += (double)masked_row_sum<T>(sh.c_b0[lane], r.acc);
+        corr = (double)masked_row_sum<T>(sh.c_b0[lane], r.acc);
         ovb |= ((r.acc & ovt0) | (~r.acc & ovo0)) != 0;
     }
-
-    // ---- sequential decisions inside the group by fixed-point iteration
-    const double lq = cd.lB * qd;
-    const bool can = valid && !wall && !ovb;
-    uint64_t acc = 0;
-    double dE = lq * St;
-    bool dec = can && (dE <= 0.0 || dE < thr);
-    int it = 1;
-    {
+    if (early) {
+        // exact energy change of the (already decided) trials
+        const T own = acc ? masked_row_sum<T>(sh.c_own[lane], acc) : (T)0;
+        dE = lq * ((St + corr) + (double)own);
+        it = 1;
+    } else {
+        // sequential decisions inside the group by fixed-point iteration
+        St += corr;
+        const bool can2 = valid && !wall && !ovb;
+        dE = lq * St;
+        dec = can2 && (dE <= 0.0 || dE < thr);
+        it = 1;
         uint64_t nacc = __ballot(dec);
         while (nacc != acc && it <= kGroup + 1) {
             acc = nacc;
             const T own = masked_row_sum<T>(sh.c_own[lane], acc);
             const bool ovown = ((acc & ovt) | (~acc & ovo)) != 0;
             dE = lq * (St + (double)own);
-            dec = can && !ovown && (dE <= 0.0 || dE < thr);
+            dec = can2 && !ovown && (dE <= 0.0 || dE < thr);
             nacc = __ballot(dec);
             ++it;
         }
         acc = nacc;
+        publish_group<T>(rec_r, pos_r, g, s, npad, ion, acc, dec, xi, yi, zi, txi, tyi, tzi);
+#ifdef MC_TIMELINE
+        tl3 = wall_clock64();
+#endif
     }
     const uint64_t m_ov = __ballot(valid && !wall && (ovb || ((acc & ovt) | (~acc & ovo)) != 0));
 
@@ -322,18 +392,6 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
         __hip_atomic_store(&sh.consumed, t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 
-    // ---- publish the decisions at once; the positions follow
-    if (lane == 0) {
-        GroupRec r;
-        r.tag = (uint32_t)(g + 1);
-        r.spare = 0;
-        r.acc = acc;
-        store_rec(rec_r, (uint32_t)(g & (kRing - 1)), r);
-    }
-    if (dec)
-        IO::store(pos_r, (uint32_t)((s & 1) * npad + ion), txi, tyi, tzi, (uint32_t)s);
-    else
-        IO::store(pos_r, (uint32_t)((s & 1) * npad + ion), xi, yi, zi, (uint32_t)s);
     __builtin_amdgcn_s_setprio(0);
 #ifdef MC_TIMELINE
     if (lane == 0 && 4 * (g + 1) <= cd.trace_cap) {
@@ -341,7 +399,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
         tl[0] = tl0;
         tl[1] = tl1;
         tl[2] = tl2;
-        tl[3] = wall_clock64();
+        tl[3] = tl3;
     }
 #endif
 
@@ -365,6 +423,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
     c_wall += __popcll(m_wall);
     c_ov += __popcll(m_ov);
     c_iters += it;
+    c_early += early ? 1 : 0;
 }
 
 // Occupancy asked of the compiler (waves per SIMD): two workgroups per CU.
@@ -405,7 +464,7 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
     }
     __syncthreads();
 
-    unsigned long long c_moves = 0, c_acc = 0, c_wall = 0, c_ov = 0, c_iters = 0;
+    unsigned long long c_moves = 0, c_acc = 0, c_wall = 0, c_ov = 0, c_iters = 0, c_early = 0;
     {
         int t = 0;
         for (int64_t g = g_begin + k_wg; g < g_end; g += cd.wg_count, ++t) {
@@ -596,6 +655,20 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
             sh.ovt_own[wave][lane] = ovt_own;
             sh.ovo_b0[wave][lane] = ovo_band[0];
             sh.ovt_b0[wave][lane] = ovt_band[0];
+            {
+                T bp = 0, bn = 0, op = 0, on = 0;
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    bp += c_band[0][m] > 0 ? c_band[0][m] : (T)0;
+                    bn += c_band[0][m] < 0 ? c_band[0][m] : (T)0;
+                    op += c_own[m] > 0 ? c_own[m] : (T)0;
+                    on += c_own[m] < 0 ? c_own[m] : (T)0;
+                }
+                sh.part_pn[wave][0][lane] = bp;
+                sh.part_pn[wave][1][lane] = bn;
+                sh.part_pn[wave][2][lane] = op;
+                sh.part_pn[wave][3][lane] = on;
+            }
 #pragma unroll
             for (int m = 0; m < P; ++m) {
                 sh.c_own[lane][wave * P + m] = c_own[m];
@@ -608,7 +681,7 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
             // ---- wave 0 finishes the group: decisions and publication
             if (wave == 0)
                 chain_step<T, M>(sh, cd, pos_r, rec_r, charge, g_begin, g, t, xi, yi, zi, txi, tyi, tzi,
-                                 wd.w, ctl, c_moves, c_acc, c_wall, c_ov, c_iters);
+                                 wd.w, ctl, c_moves, c_acc, c_wall, c_ov, c_iters, c_early);
         }
     }
     if (wave == 0 && lane == 0 && c_moves) {
@@ -618,6 +691,7 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
         atomicAdd(&cd.stats[3], c_ov);
         atomicAdd(&cd.stats[4], c_moves - c_acc - c_wall - c_ov);
         atomicAdd(&cd.stats[5], c_iters);
+        atomicAdd(&cd.stats[6], c_early);
     }
 }
 

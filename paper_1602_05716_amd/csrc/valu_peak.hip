@@ -10,6 +10,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 
 #define CHECK(x)                                                                          \
     do {                                                                                  \
@@ -76,6 +77,12 @@ __global__ void __launch_bounds__(256) mixed(float* out, float seed) {
     out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+// plain streaming copy, used to calibrate the HBM traffic counters
+__global__ void __launch_bounds__(256) copy_f4(const float4* __restrict__ a, float4* __restrict__ b, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
 template <typename K>
 double time_ms(K kernel, int blocks, float* out) {
     hipEvent_t e0, e1;
@@ -98,7 +105,21 @@ double time_ms(K kernel, int blocks, float* out) {
     return best;
 }
 
-int main() {
+int main(int argc, char** argv) {
+    if (argc > 1 && std::string(argv[1]) == "--copy") {
+        // 256 MiB read + 256 MiB written, one launch
+        const size_t n = (size_t)256 << 20 >> 4;
+        float4 *a = nullptr, *b = nullptr;
+        CHECK(hipMalloc(&a, n * sizeof(float4)));
+        CHECK(hipMalloc(&b, n * sizeof(float4)));
+        CHECK(hipMemset(a, 1, n * sizeof(float4)));
+        hipLaunchKernelGGL(copy_f4, dim3(8192), dim3(256), 0, 0, a, b, n);
+        CHECK(hipDeviceSynchronize());
+        std::printf("{\"copy_bytes_read\": %zu, \"copy_bytes_written\": %zu}\n", n * sizeof(float4), n * sizeof(float4));
+        CHECK(hipFree(a));
+        CHECK(hipFree(b));
+        return 0;
+    }
     hipDeviceProp_t p;
     CHECK(hipGetDeviceProperties(&p, 0));
     const int cus = p.multiProcessorCount;

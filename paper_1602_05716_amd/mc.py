@@ -45,6 +45,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("moves", ctypes.c_int64), ("accepted", ctypes.c_int64),
                 ("rejected_wall", ctypes.c_int64), ("rejected_overlap", ctypes.c_int64),
                 ("rejected_metropolis", ctypes.c_int64), ("fixpoint_iterations", ctypes.c_int64),
+                ("early_groups", ctypes.c_int64),
                 ("resums", ctypes.c_int64), ("last_drift", ctypes.c_double),
                 ("max_abs_drift", ctypes.c_double), ("band", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("workgroups", ctypes.c_int32),
