@@ -29,10 +29,48 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MC moves/s + pair terms/s at N=32768; ESS/s plain vs batched vs surrogate-DA"
 CUS, CLOCK_HZ = 256, 2.4e9
-# v_rsq_f32 issue rate per CU per clock on gfx950 (lanes); the VALU probe
-# (valu_peak) measures it on the device and bench reports both.
-RSQ_LANES_PER_CLK_CU = 16.0
-RSQ_PER_PAIR = 2
+# ALU roofline of one pair term (float path).  Algorithmic work per term:
+# two squared distances (3 sub + 3 mul/fma each), the difference of the two
+# inverse distances and its charge-weighted accumulation (2), the contact
+# test (1): 15 vector ALU lane-ops, plus 2 reciprocal square roots.
+# Chip rates: the published FP32 vector peak, 157.3 TFLOP/s = 128 FMA lanes
+# per clock per CU; transcendentals at a quarter of that, 32 lanes per clock
+# per CU (the valu_peak probe measures both on the device).
+VALU_PER_PAIR, RSQ_PER_PAIR = 15, 2
+VALU_LANES_PER_CLK_CU, RSQ_LANES_PER_CLK_CU = 128.0, 32.0
+PAIR_PEAK_PER_S = CUS * CLOCK_HZ / (VALU_PER_PAIR / VALU_LANES_PER_CLK_CU + RSQ_PER_PAIR / RSQ_LANES_PER_CLK_CU)
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_kernel_n32768_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1602_05716_amd", "csrc", f)
+                  for f in ("mc_sweep_kernel.hpp", "mc_device.hpp")]
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch(sweeps_per_launch):
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated on a copy kernel); None when the summary is absent
+    or was taken on a different version of the sweep kernel."""
+    try:
+        kv = {}
+        with open(TRAFFIC_SUMMARY) as fh:
+            for line in fh:
+                if line.startswith("- ") and ": " in line:
+                    k, v = line[2:].split(": ", 1)
+                    kv[k.strip()] = v.strip().strip("`")
+        if kv.get("kernel_source_digest") != kernel_source_digest():
+            return None
+        return float(kv["hbm_bytes_per_sweep"]) * sweeps_per_launch
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -143,11 +181,12 @@ def main():
 
     # dominant kernel: the persistent sweep kernel, timed by HIP events on its stream
     avg_launch_s = kernel_ms * 1e-3 / max(1, launches)
-    per_launch_rsq = (kernel_sweeps / max(1, launches)) * n * (n - 1) * RSQ_PER_PAIR
-    achieved = per_launch_rsq / avg_launch_s / 1e12
-    peak = CUS * CLOCK_HZ * RSQ_LANES_PER_CLK_CU / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Trsqrt/s",
-                "frac": achieved / peak, "traffic": None,
+    per_launch_pairs = (kernel_sweeps / max(1, launches)) * n * (n - 1)
+    achieved = per_launch_pairs / avg_launch_s / 1e12
+    peak = PAIR_PEAK_PER_S / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tpairterm/s",
+                "frac": achieved / peak, "traffic": traffic_per_launch(kernel_sweeps / max(1, launches)),
+                "per_unit": "pair term = %d VALU + %d rsq lane-ops" % (VALU_PER_PAIR, RSQ_PER_PAIR),
                 "kernel": "sweep_kernel<float,%d>" % st1["waves"],
                 "avg_launch_ms": avg_launch_s * 1e3, "launches": launches,
                 "sweeps_per_launch": kernel_sweeps / max(1, launches)}

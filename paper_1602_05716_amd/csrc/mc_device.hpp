@@ -44,6 +44,8 @@ template <> struct Prec<float> {
         return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
     }
     static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    // operands are never NaN here: one v_min instruction
+    static __device__ __forceinline__ float min(float a, float b) { return __builtin_fminf(a, b); }
 };
 
 template <> struct Prec<double> {
@@ -55,6 +57,7 @@ template <> struct Prec<double> {
     }
     // the double path keeps the textbook rounding: product, then sum
     static __device__ __forceinline__ double fma(double a, double b, double c) { return a * b + c; }
+    static __device__ __forceinline__ double min(double a, double b) { return __builtin_fmin(a, b); }
 };
 
 template <typename T>

@@ -25,11 +25,14 @@
 //     trial position), so that once j's accept bit is known only a select and
 //     an add remain on the critical path.
 //   * The waves hand their partial sums and candidate corrections over
-//     through LDS and move on to their next target; wave 0 then waits for
-//     group g-1's accept mask, then finds the group's own accept bits by iterating
-//     the sequential rule a_i = f_i(a_0..a_{i-1}) to its fixed point (Jacobi
-//     sweeps over the wave; the fixed point is unique, equals the sequential
-//     outcome and is reached in at most 64 iterations, usually two).
+//     through LDS and move on to their next target; they never wait for an
+//     accept mask.  Wave 0 then decides the group: if the threshold lies
+//     outside the interval spanned by the unknown corrections for every
+//     lane, at once; otherwise it waits for the band groups' accept masks
+//     and finds the group's own accept bits by iterating the sequential rule
+//     a_i = f_i(a_0..a_{i-1}) to its fixed point (Jacobi sweeps over the
+//     wave; the fixed point is unique, equals the sequential outcome and is
+//     reached in at most 64 iterations, usually two).
 //   * Publication: the accept mask goes out at once in the group record; the
 //     new positions are written in place, double buffered by sweep parity,
 //     each 16-byte record carrying the sweep index of the trial that produced
@@ -166,17 +169,17 @@ struct SweepShared {
     // hand-off from the compute waves to the chain wave (one target at a time)
     double part_s[M][kGroup];   // partial sums over each wave's partners
     uint64_t part_ov[M];        // overlap ballots over final partners
-    T part_pn[M][4][kGroup];    // per wave: sums of the positive / negative
-                                // corrections of group g-1 and of the own group
+    T part_pn[M][2][kGroup];    // per wave: sums of the positive / negative
+                                // corrections still unknown (band groups, own group)
     SB ovo_own[M][kGroup];      // own group, j < i: overlap with j's old position
     SB ovt_own[M][kGroup];      //                   overlap with j's trial position
-    SB ovo_b0[M][kGroup];       // group g-1: overlap with old / trial position
-    SB ovt_b0[M][kGroup];
+    SB ovo_b[kMaxBand][M][kGroup];  // group g-1-kb: overlap with j's old / trial position
+    SB ovt_b[kMaxBand][M][kGroup];
     // corrections, one padded row per mover i (16-byte reads of 4 partners
     // are free of bank conflicts)
     static constexpr int CS = kGroup + (sizeof(T) == 4 ? 4 : 2);
-    T c_own[kGroup][CS];        // own group [mover i][partner j]
-    T c_b0[kGroup][CS];         // group g-1 [mover i][partner j]
+    T c_own[kGroup][CS];           // own group [mover i][partner j]
+    T c_b[kMaxBand][kGroup][CS];   // group g-1-kb [mover i][partner j]
     int ready;                  // compute waves done filling the hand-off for the current target
     int consumed;               // local target index + 1 the chain wave last released
 };
@@ -247,8 +250,9 @@ __device__ __forceinline__ void publish_group(__amdgpu_buffer_rsrc_t rec_r, __am
 }
 
 // The sequential part of target group g, run by wave 0 after its own share
-// of the pair terms: combine the waves' hand-off, wait for group g-1's accept
-// mask, decide the group by fixed-point iteration and publish.
+// of the pair terms: combine the waves' hand-off, decide the group (from the
+// bounds, or after the band groups' accept masks by fixed-point iteration)
+// and publish.
 template <typename T, int M>
 __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDesc& cd,
                                            __amdgpu_buffer_rsrc_t pos_r, __amdgpu_buffer_rsrc_t rec_r,
@@ -290,31 +294,36 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
     tl1 = wall_clock64();
 #endif
     double St = 0.0;
-    uint64_t ovo = 0, ovt = 0, ovo0 = 0, ovt0 = 0;
+    uint64_t ovo = 0, ovt = 0, ovob[kMaxBand], ovtb[kMaxBand];
     bool ovb = false;
-    T bp = 0, bn = 0, op = 0, on = 0;
+    T cp = 0, cn = 0;
+#pragma unroll
+    for (int kb = 0; kb < kMaxBand; ++kb) ovob[kb] = ovtb[kb] = 0;
 #pragma unroll
     for (int w = 0; w < M; ++w) {
-        bp += sh.part_pn[w][0][lane];
-        bn += sh.part_pn[w][1][lane];
-        op += sh.part_pn[w][2][lane];
-        on += sh.part_pn[w][3][lane];
+        cp += sh.part_pn[w][0][lane];
+        cn += sh.part_pn[w][1][lane];
         St += sh.part_s[w][lane];
         ovb |= ((sh.part_ov[w] >> lane) & 1ull) != 0;
         ovo |= (uint64_t)sh.ovo_own[w][lane] << (w * P);
         ovt |= (uint64_t)sh.ovt_own[w][lane] << (w * P);
-        ovo0 |= (uint64_t)sh.ovo_b0[w][lane] << (w * P);
-        ovt0 |= (uint64_t)sh.ovt_b0[w][lane] << (w * P);
+#pragma unroll
+        for (int kb = 0; kb < kMaxBand; ++kb) {
+            ovob[kb] |= (uint64_t)sh.ovo_b[kb][w][lane] << (w * P);
+            ovtb[kb] |= (uint64_t)sh.ovt_b[kb][w][lane] << (w * P);
+        }
     }
 
-    // ---- decisions.  dE = lB q (St + corr_{g-1} + own) with corr_{g-1} and
-    // own unknown until group g-1's and this group's accept bits are known,
-    // but bounded by the sums of their negative and positive terms.  When the
+    // ---- decisions.  dE = lB q (St + sum_kb corr_{g-1-kb} + own): the band
+    // corrections and the own-group term stay unknown until the accept bits
+    // of groups g-band..g-1 and of this group are known, but they are bounded
+    // by the sums of their negative and positive candidate terms.  When the
     // threshold lies outside every lane's interval (with a margin far larger
     // than the rounding of these sums) and no hard-core overlap can flip, the
-    // group's decisions are certain and are published before group g-1's
-    // accept mask has even arrived; the exact dE follows.  Otherwise: wait
-    // for group g-1 and iterate the sequential rule to its fixed point.
+    // group's decisions are certain and are published before the band
+    // groups' accept masks have even arrived; the exact dE follows.
+    // Otherwise: wait for the band groups and iterate the sequential rule to
+    // its fixed point.
     __builtin_amdgcn_s_setprio(3);
     const double lq = cd.lB * qd;
     const bool can = valid && !wall && !ovb;
@@ -324,15 +333,18 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
     int it = 0;
     bool early = false;
     {
-        const bool use_b0 = band >= 1;
-        const double lo = St + (use_b0 ? (double)bn : 0.0) + (double)on;
-        const double hi = St + (use_b0 ? (double)bp : 0.0) + (double)op;
+        const double lo = St + (double)cn;
+        const double hi = St + (double)cp;
         const double e_lo = lq >= 0 ? lq * lo : lq * hi;
         const double e_hi = lq >= 0 ? lq * hi : lq * lo;
-        const double span = (double)((use_b0 ? bp - bn : (T)0) + (op - on));
+        const double span = (double)(cp - cn);
         const double margin = fabs(lq) * (1e-4 * span + 1e-9 * (fabs(St) + 1.0)) + 1e-12;
-        const uint64_t ov_sure = use_b0 ? (ovo0 & ovt0) : 0ull;
-        const uint64_t ov_flip = (use_b0 ? (ovo0 ^ ovt0) : 0ull) | (ovo ^ ovt);
+        uint64_t ov_sure = 0, ov_flip = ovo ^ ovt;
+#pragma unroll
+        for (int kb = 0; kb < kMaxBand; ++kb) {
+            ov_sure |= ovob[kb] & ovtb[kb];
+            ov_flip |= ovob[kb] ^ ovtb[kb];
+        }
         const bool reject_sure = !can || ov_sure != 0 || (ovo & ovt) != 0;
         const bool accept_sure = !reject_sure && ov_flip == 0 && e_hi < thr - margin;
         const bool sure = reject_sure || accept_sure || (ov_flip == 0 && e_lo >= thr + margin);
@@ -346,14 +358,18 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
 #endif
         }
     }
+    // band corrections, oldest group first
     double corr = 0.0;
-    if (band >= 1) {
-        const GroupRec r = wait_rec(rec_r, g - 1, ctl);
+#pragma unroll
+    for (int kb = kMaxBand - 1; kb >= 0; --kb) {
+        if (kb < band) {
+            const GroupRec r = wait_rec(rec_r, g - 1 - kb, ctl);
 #ifdef MC_TIMELINE
-        tl2 = wall_clock64();
+            if (kb == 0) tl2 = wall_clock64();
 #endif
-        corr = (double)masked_row_sum<T>(sh.c_b0[lane], r.acc);
-        ovb |= ((r.acc & ovt0) | (~r.acc & ovo0)) != 0;
+            corr += (double)masked_row_sum<T>(sh.c_b[kb][lane], r.acc);
+            ovb |= ((r.acc & ovtb[kb]) | (~r.acc & ovob[kb])) != 0;
+        }
     }
     if (early) {
         // exact energy change of the (already decided) trials
@@ -586,6 +602,9 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
                 const int jl = wave * P + (lane < P ? lane : 0);
                 typename IO::Rec nxt{};
                 bool have_next = false;
+                // uniform diameters: overlap with any of these partners iff the
+                // smallest trial distance is below the contact distance
+                T d2t_min = (T)3.0e38;
                 for (int64_t gp = g - nb + 1; gp <= g_last; ++gp) {
                     const int j = bp * kGroup + jl;
                     typename IO::Rec cur;
@@ -620,29 +639,19 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
                         const T d2 = Prec<T>::norm2(p.x - xi, p.y - yi, p.z - zi);
                         const T d2t = Prec<T>::norm2(p.x - txi, p.y - tyi, p.z - tzi);
                         sf = Prec<T>::fma(p.w, Prec<T>::rinv(d2t) - Prec<T>::rinv(d2), sf);
-                        ov |= d2t < s_ij * s_ij;
+                        if (UNIFORM_SIGMA)
+                            d2t_min = Prec<T>::min(d2t, d2t_min);
+                        else
+                            ov |= d2t < s_ij * s_ij;
                     }
                     S += (double)sf;
                     wave_lds_sync();
                     bp = bn;
                     sp = sn;
                 }
+                if (UNIFORM_SIGMA) ov |= d2t_min < (hu + hu) * (hu + hu);
             }
 
-            // ---- band groups g-band..g-2 are decided well before g: apply them here
-#pragma unroll
-            for (int kb = kMaxBand - 1; kb >= 1; --kb) {
-                if (kb < band) {
-                    const GroupRec r = wait_rec(rec_r, g - 1 - kb, ctl);
-                    const uint32_t a = (uint32_t)(r.acc >> (wave * P)) & (uint32_t)((1ull << P) - 1);
-                    T cf = 0;
-#pragma unroll
-                    for (int m = 0; m < P; ++m)
-                        if ((a >> m) & 1u) cf += c_band[kb][m];
-                    S += (double)cf;
-                    ov |= ((((SB)a & ovt_band[kb]) | ((SB)~a & ovo_band[kb])) != 0);
-                }
-            }
 
             // ---- hand off to the chain wave once it has released the previous target
             wait_lds_at_least(&sh.consumed, t, ctl);
@@ -653,26 +662,33 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
             }
             sh.ovo_own[wave][lane] = ovo_own;
             sh.ovt_own[wave][lane] = ovt_own;
-            sh.ovo_b0[wave][lane] = ovo_band[0];
-            sh.ovt_b0[wave][lane] = ovt_band[0];
+#pragma unroll
+            for (int kb = 0; kb < kMaxBand; ++kb) {
+                sh.ovo_b[kb][wave][lane] = ovo_band[kb];
+                sh.ovt_b[kb][wave][lane] = ovt_band[kb];
+            }
             {
-                T bp = 0, bn = 0, op = 0, on = 0;
+                // candidate corrections are zero outside the band
+                T cp = 0, cn = 0;
 #pragma unroll
                 for (int m = 0; m < P; ++m) {
-                    bp += c_band[0][m] > 0 ? c_band[0][m] : (T)0;
-                    bn += c_band[0][m] < 0 ? c_band[0][m] : (T)0;
-                    op += c_own[m] > 0 ? c_own[m] : (T)0;
-                    on += c_own[m] < 0 ? c_own[m] : (T)0;
+#pragma unroll
+                    for (int kb = 0; kb < kMaxBand; ++kb) {
+                        cp += c_band[kb][m] > 0 ? c_band[kb][m] : (T)0;
+                        cn += c_band[kb][m] < 0 ? c_band[kb][m] : (T)0;
+                    }
+                    cp += c_own[m] > 0 ? c_own[m] : (T)0;
+                    cn += c_own[m] < 0 ? c_own[m] : (T)0;
                 }
-                sh.part_pn[wave][0][lane] = bp;
-                sh.part_pn[wave][1][lane] = bn;
-                sh.part_pn[wave][2][lane] = op;
-                sh.part_pn[wave][3][lane] = on;
+                sh.part_pn[wave][0][lane] = cp;
+                sh.part_pn[wave][1][lane] = cn;
             }
 #pragma unroll
             for (int m = 0; m < P; ++m) {
                 sh.c_own[lane][wave * P + m] = c_own[m];
-                sh.c_b0[lane][wave * P + m] = c_band[0][m];
+#pragma unroll
+                for (int kb = 0; kb < kMaxBand; ++kb)
+                    if (kb < band) sh.c_b[kb][lane][wave * P + m] = c_band[kb][m];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             if (lane == 0)
