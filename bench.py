@@ -68,7 +68,7 @@ def traffic_per_launch(sweeps_per_launch):
                     kv[k.strip()] = v.strip().strip("`")
         if kv.get("kernel_source_digest") != kernel_source_digest():
             return None
-        return float(kv["hbm_bytes_per_sweep"]) * sweeps_per_launch
+        return float(kv["hbm_bytes_per_launch_fixed"]) + float(kv["hbm_bytes_per_sweep"]) * sweeps_per_launch
     except (OSError, KeyError, ValueError):
         return None
 
@@ -187,6 +187,7 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tpairterm/s",
                 "frac": achieved / peak, "traffic": traffic_per_launch(kernel_sweeps / max(1, launches)),
                 "per_unit": "pair term = %d VALU + %d rsq lane-ops" % (VALU_PER_PAIR, RSQ_PER_PAIR),
+                "rsq_only_frac": achieved * RSQ_PER_PAIR / (CUS * CLOCK_HZ * RSQ_LANES_PER_CLK_CU / 1e12),
                 "kernel": "sweep_kernel<float,%d>" % st1["waves"],
                 "avg_launch_ms": avg_launch_s * 1e3, "launches": launches,
                 "sweeps_per_launch": kernel_sweeps / max(1, launches)}
