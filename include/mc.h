@@ -218,6 +218,87 @@ int mc_timing_reset(mc_handle* h);
  * warm-up tuning); max_disp > 0. */
 int mc_set_max_disp(mc_handle* h, double max_disp);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent chains in one persistent launch.
+ *
+ * Every chain of a batch is an independent Metropolis chain as above; the
+ * sweep kernel serves all of them in one cooperative launch, each chain with
+ * its own workgroups (a multi-workgroup-per-chain analogue of the paper's
+ * multi-thread-per-particle treatment, Sec. 3.7, whose best setting depends
+ * on N, Sec. 4).  The calls without a chain index act on chain 0; mc_sweep,
+ * mc_set_max_disp, mc_rdf_sample, mc_rdf_reset and the timing calls act on
+ * every chain.  All chains share the precision, the options and the sweep
+ * counter; their random streams differ by chain_id (Philox counter word 2).
+ * ------------------------------------------------------------------------ */
+typedef struct mc_chain_spec {
+    int32_t n;               /* ions, 1 <= n <= 2^24                              */
+    int32_t reserved0;
+    const double* charges;   /* [n], as for mc_create                            */
+    const double* diameters; /* [n]                                              */
+    const double* positions; /* [n*3]                                            */
+    double radius;           /* wall radius                                      */
+    double l_B;              /* Bjerrum length                                   */
+    double max_disp;         /* trial-cube half side; 0 = the options' max_disp  */
+    uint32_t chain_id;       /* Philox counter word 2 of this chain              */
+    int32_t reserved1;
+} mc_chain_spec;
+
+/*
+ * Creates a batch of n_chains >= 1 chains.  Each spec is validated as by
+ * mc_create (errors name the chain); the caller keeps ownership of every
+ * array.  The number of chains may not exceed the number of workgroups that
+ * can be resident at once (MC_E_ARG).  opt->workgroups, if > 0, caps the
+ * total workgroups of the launch.  The initial schedule gives each chain
+ * workgroups by the default cost model (see mc_autotune).
+ */
+int mc_create_batch(int32_t n_chains, const mc_chain_spec* chains, const mc_options* opt,
+                    mc_handle** out);
+
+/* Number of chains of the handle. */
+int mc_chain_count(const mc_handle* h, int32_t* n_chains);
+
+/* Per-chain versions of mc_energy, mc_rdf, mc_species, mc_get_positions,
+ * mc_trace, mc_energy_series, mc_get_stats and mc_set_max_disp; chain is in
+ * [0, n_chains), MC_E_ARG otherwise. */
+int mc_chain_energy(mc_handle* h, int32_t chain, double* e_running, double* e_exact);
+int mc_chain_rdf(mc_handle* h, int32_t chain, int32_t bins, double* g, uint64_t* counts,
+                 uint64_t* centres, int64_t* n_samples);
+int mc_chain_species(const mc_handle* h, int32_t chain, int32_t* ntypes, double* charges,
+                     double* diameters);
+int mc_chain_positions(mc_handle* h, int32_t chain, double* xyz);
+int mc_chain_trace(mc_handle* h, int32_t chain, int64_t n_moves, uint8_t* acc, double* dE);
+int mc_chain_energy_series(mc_handle* h, int32_t chain, int64_t n, double* e);
+int mc_chain_stats(mc_handle* h, int32_t chain, mc_stats* out);
+int mc_chain_set_max_disp(mc_handle* h, int32_t chain, double max_disp);
+
+/*
+ * Schedule of the batch: workgroups [n_chains] (nullable) receives each
+ * chain's workgroup count; model [2] (nullable) the cost model in use,
+ * a and b in microseconds, of the per-sweep time t(B, w) = a B + b B^2 / w
+ * of a chain of B groups of 64 ions served by w workgroups.  Schedules only
+ * change speed: a chain's trajectory does not depend on them.
+ */
+int mc_get_schedule(const mc_handle* h, int32_t* workgroups, double* model);
+
+/* Sets each chain's workgroup count, workgroups [n_chains], each in
+ * [1, groups of 64 of the chain], total at most the co-resident capacity. */
+int mc_set_schedule(mc_handle* h, const int32_t* workgroups);
+
+/* Synchronises and reports, per chain, the device time in milliseconds of
+ * the last sweep launch from its start to the chain's last decision,
+ * ms [n_chains]. */
+int mc_chain_launch_ms(mc_handle* h, double* ms);
+
+/*
+ * Autotuner: runs one launch of calib_sweeps sweeps of every chain (real
+ * sweeps that continue the chains, keyed by seed), fits the cost model's a
+ * and b to the measured per-chain times by least squares on relative error,
+ * then gives each chain workgroups by water filling of the co-resident
+ * capacity (each step gives one more workgroup to the chain the model says
+ * finishes last).  model [2] (nullable) receives the fit.
+ */
+int mc_autotune(mc_handle* h, int32_t calib_sweeps, uint64_t seed, double* model);
+
 /* Releases every resource of the handle; NULL is allowed. */
 void mc_destroy(mc_handle* h);
 

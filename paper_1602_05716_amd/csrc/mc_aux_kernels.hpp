@@ -6,7 +6,7 @@
 // correlation functions are measured on ions away from the wall.
 #pragma once
 
-#include "mc_device.hpp"
+#include "mc_sweep_kernel.hpp"
 
 namespace mcdev {
 
@@ -18,22 +18,34 @@ struct EnergyAux {
     unsigned long long n_resum;
 };
 
+// Work item of a batched auxiliary launch: chain index and the block's index
+// inside that chain.
+struct BlockItem {
+    int32_t chain;
+    int32_t part;
+};
+
 // Positions are read as {x, y, z, *} records (the fourth word is the sweep
-// version tag of the sweep kernel) and charges from their own array.
-// E = l_B sum_{i<j} q_i q_j / r_ij, every term formed exactly as
-// (q_i q_j) / sqrt(d2) in double.  Block p handles the row groups p and
-// nb-1-p (so every block does nb+1 tiles); wave w of the block takes the
-// tiles t = row + w, row + w + 4, ...  partial[p] receives the block's sum.
+// version tag of the sweep kernel) from the image of the given parity, and
+// charges from their own array.  E = l_B sum_{i<j} q_i q_j / r_ij, every term
+// formed exactly as (q_i q_j) / sqrt(d2) in double.  Block p of a chain
+// handles the row groups p and nb-1-p (so every block does nb+1 tiles); wave
+// w of the block takes the tiles t = row + w, row + w + 4, ...  The chain's
+// e_partial[p] receives the block's sum.
 template <typename T>
 __global__ void __launch_bounds__(256)
-energy_partial_kernel(const typename Prec<T>::T4* __restrict__ pos, const T* __restrict__ charge,
-                      int nb, double* __restrict__ partial)
+energy_partial_kernel(const ChainDesc* __restrict__ chains, const BlockItem* __restrict__ items, int parity)
 {
     using T4 = typename Prec<T>::T4;
     __shared__ double st[4][kGroup][4];
     __shared__ double wsum[4];
+    const BlockItem it = items[blockIdx.x];
+    const ChainDesc& cd = chains[it.chain];
+    const int nb = cd.nb;
+    const T4* __restrict__ pos = (const T4*)cd.pos + (size_t)parity * nb * kGroup;
+    const T* __restrict__ charge = (const T*)cd.charge;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int p = blockIdx.x;
+    const int p = it.part;
     double acc = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
         const int row = pass == 0 ? p : nb - 1 - p;
@@ -65,51 +77,60 @@ energy_partial_kernel(const typename Prec<T>::T4* __restrict__ pos, const T* __r
     const double ws = __shfl(wave_sum(acc), 0, 64);
     if (lane == 0) wsum[wave] = ws;
     __syncthreads();
-    if (threadIdx.x == 0) partial[p] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    if (threadIdx.x == 0) cd.e_partial[p] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
 }
 
-// Sums the block partials in a fixed order, records the drift of the running
-// energy and, when `reset` is set, makes the re-sum the new running energy.
-__global__ void energy_finalize_kernel(const double* __restrict__ partial, int nparts, double lB,
-                                       double* e_state, EnergyAux* aux, int reset, int record_drift)
+// One block per chain: sums the chain's partials in a fixed order, records
+// the drift of the running energy and, when `reset` is set, makes the re-sum
+// the new running energy.
+__global__ void energy_finalize_kernel(const ChainDesc* __restrict__ chains, int reset, int record_drift)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (threadIdx.x != 0) return;
+    const ChainDesc& cd = chains[blockIdx.x];
+    EnergyAux* aux = (EnergyAux*)cd.aux;
+    const int nparts = (cd.nb + 1) / 2;
     double e = 0.0;
-    for (int k = 0; k < nparts; ++k) e += partial[k];
-    e *= lB;
+    for (int k = 0; k < nparts; ++k) e += cd.e_partial[k];
+    e *= cd.lB;
     aux->e_resum = e;
     if (record_drift) {
-        const double d = *e_state - e;
+        const double d = *cd.e_state - e;
         aux->drift_last = d;
         const double ad = d < 0 ? -d : d;
         if (ad > aux->drift_max) aux->drift_max = ad;
         aux->n_resum += 1;
     }
-    if (reset) *e_state = e;
+    if (reset) *cd.e_state = e;
 }
 
 // Pair counts for g_ab(r): centre i needs |x_i| <= R - rmax (the wall
 // exclusion of Sec. 5.2), neighbours are all j != i; bin k = floor(r / dr)
 // for r < rmax.  Distances and bins are formed in double exactly as written
 // (no fused multiply-add), so the integer counts do not depend on the
-// kernel's tiling.  One block of 4 waves per group of 64 centres; each wave
-// takes every 4th partner tile; counts go to an LDS histogram first.
+// kernel's tiling.  One block of 4 waves per group of 64 centres of a chain;
+// each wave takes every 4th partner tile; counts go to an LDS histogram
+// first.
 template <typename T>
 __global__ void __launch_bounds__(256)
-rdf_kernel(const typename Prec<T>::T4* __restrict__ pos, const int32_t* __restrict__ type,
-           int n, int nb, int ntypes, double rc, double rmax, double dr, int bins,
-           unsigned long long* __restrict__ counts, unsigned long long* __restrict__ centres)
+rdf_kernel(const ChainDesc* __restrict__ chains, const BlockItem* __restrict__ items, int parity,
+           double rmax, double dr, int bins)
 {
     using T4 = typename Prec<T>::T4;
     extern __shared__ unsigned int hist[];   // [ntypes*ntypes*bins]
     __shared__ double st[4][kGroup][3];
     __shared__ int stt[4][kGroup];
+    const BlockItem item = items[blockIdx.x];
+    const ChainDesc& cd = chains[item.chain];
+    const int n = cd.n, nb = cd.nb, ntypes = cd.ntypes;
+    const T4* __restrict__ pos = (const T4*)cd.pos + (size_t)parity * nb * kGroup;
+    const int32_t* __restrict__ type = cd.type;
+    const double rc = cd.rdf_rc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nh = ntypes * ntypes * bins;
     for (int k = threadIdx.x; k < nh; k += blockDim.x) hist[k] = 0u;
     __syncthreads();
 
-    const int row = blockIdx.x;
+    const int row = item.part;
     const int i = row * kGroup + lane;
     const T4 xi4 = pos[i];
     const double xi = (double)xi4.x, yi = (double)xi4.y, zi = (double)xi4.z;
@@ -123,7 +144,7 @@ rdf_kernel(const typename Prec<T>::T4* __restrict__ pos, const int32_t* __restri
             // centres of this block by type
             for (int a = 0; a < ntypes; ++a) {
                 const unsigned long long ca = __ballot(centre && ti == a);
-                if (lane == 0 && ca) atomicAdd(&centres[a], (unsigned long long)__popcll(ca));
+                if (lane == 0 && ca) atomicAdd(&cd.rdf_centres[a], (unsigned long long)__popcll(ca));
             }
         }
     }
@@ -157,7 +178,7 @@ rdf_kernel(const typename Prec<T>::T4* __restrict__ pos, const int32_t* __restri
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nh; k += blockDim.x)
-        if (hist[k]) atomicAdd(&counts[k], (unsigned long long)hist[k]);
+        if (hist[k]) atomicAdd(&cd.rdf_counts[k], (unsigned long long)hist[k]);
 }
 
 }  // namespace mcdev

@@ -2,10 +2,12 @@
 // instantiations for gfx950.
 //
 // Paper: Liang, Xing, Li, arXiv:1602.05716 (see include/mc.h for the
-// passages each entry point follows).  The host never touches the chain
-// between trials: mc_sweep enqueues one persistent cooperative launch per
-// stretch of sweeps, interleaved with the double-precision energy re-sum and
-// g(r) sampling kernels, all on the handle's stream.
+// passages each entry point follows).  A handle holds one or more
+// independent chains; the host never touches a chain between trials:
+// mc_sweep enqueues one persistent cooperative launch per stretch of sweeps
+// that serves every chain of the handle, interleaved with the
+// double-precision energy re-sum and g(r) sampling kernels, all on the
+// handle's stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,11 +15,11 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
-#include <map>
 #include <new>
+#include <queue>
 #include <string>
-#include <tuple>
 #include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "../../include/mc.h"
@@ -32,6 +34,11 @@ thread_local std::string g_create_error = "no error";
 
 // Stats slots written by the sweep kernel.
 enum { ST_MOVES = 0, ST_ACC, ST_WALL, ST_OVERLAP, ST_METRO, ST_ITERS, ST_EARLY, ST_N };
+
+constexpr int64_t kMaxLaunchSweeps = 4096;
+// Default cost model of a chain (microseconds): per-sweep time
+// t(nb, w) = a nb + b nb^2 / w for nb groups of 64 served by w workgroups.
+constexpr double kModelA = 2.5, kModelB = 0.7;
 
 struct DeviceInfo {
     int device = -1;
@@ -60,7 +67,7 @@ bool device_info(DeviceInfo& di, std::string& err) {
     return true;
 }
 
-using SweepFn = void (*)(const ChainDesc*, const int32_t*, uint32_t, int32_t, Ctl);
+using SweepFn = void (*)(const ChainDesc*, const int2*, uint32_t, int32_t, Ctl);
 
 template <typename T, int M, bool U>
 SweepFn sweep_fn() {
@@ -76,22 +83,57 @@ SweepFn pick_sweep(bool fp64, int waves, bool uniform) {
     return uniform ? sweep_fn<float, 4, true>() : sweep_fn<float, 4, false>();
 }
 
+// One independent chain of a handle: host copy of its model and schedule,
+// and its device buffers (carved from the handle's arena, except the two
+// that grow).
+struct Chain {
+    int32_t n = 0, nb = 0, npad = 0;
+    double R = 0, lB = 0, D = 1.0;
+    bool uniform_sigma = true;
+    double sigma0 = 1.0;
+    uint32_t chain_id = 0;
+    int band = 0;
+    int wg = 1;
+    std::vector<std::pair<double, double>> species;  // (charge, diameter)
+    std::vector<int64_t> n_of_type;
+    std::vector<int32_t> type;
+    // device memory
+    void* pos = nullptr;          // versioned records [2][npad]
+    void* half = nullptr;         // T[npad]
+    void* charge = nullptr;       // T[npad]
+    double* wall_a = nullptr;     // [npad]
+    int32_t* d_type = nullptr;    // [npad]
+    GroupRec* rec = nullptr;      // [kRing]
+    unsigned long long* stats = nullptr;  // [ST_N]
+    unsigned long long* clk = nullptr;    // [2]
+    double* e_partial = nullptr;  // [(nb + 1) / 2]
+    EnergyAux* aux = nullptr;
+    double* e_state = nullptr;
+    double* sweep_tot = nullptr;  // [kMaxLaunchSweeps]
+    unsigned long long* rdf_counts = nullptr;
+    unsigned long long* rdf_centres = nullptr;
+    uint8_t* trace_acc = nullptr;
+    double* trace_de = nullptr;
+    int64_t trace_cap = 0;
+    double* e_series = nullptr;   // grows
+    int64_t e_capacity = 0;
+    double* de_group = nullptr;   // grows: [n_sweeps * nb] of one launch
+    int64_t de_capacity = 0;
+    ChainDesc desc{};
+};
+
 }  // namespace
 
 struct mc_handle {
-    // model
-    int32_t n = 0, nb = 0, npad = 0;
+    std::vector<Chain> chains;
     bool fp64 = false;
-    double R = 0, lB = 0, D = 1.0;
     bool uniform_sigma = true;
-    std::vector<double> q, sigma;
-    std::vector<int32_t> type;
-    std::vector<std::pair<double, double>> species;  // (charge, diameter)
-    std::vector<int64_t> n_of_type;
-    // options
+    int waves = 4;
+    int cap = 1;                  // co-resident workgroups of the sweep kernel
+    int wg_total = 1;             // workgroups of the sweep launch
+    int wg_budget = 1;            // workgroups the schedule may use
+    double model_a = kModelA, model_b = kModelB;
     mc_options opt{};
-    int band = 0, waves = 4, wg = 1;
-    // runtime
     DeviceInfo dev;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -99,38 +141,22 @@ struct mc_handle {
     int64_t sweeps = 0;
     int64_t rdf_samples = 0;
     std::string err = "no error";
-    // device memory
-    void* pos = nullptr;          // T4[2][npad]
-    void* half = nullptr;         // T[npad]
-    void* charge = nullptr;       // T[npad]
-    double* wall_a = nullptr;     // [npad]
-    int32_t* d_type = nullptr;    // [npad]
-    GroupRec* rec = nullptr;      // [kRing]
-    unsigned long long* stats = nullptr;  // [ST_N]
+    // device memory shared by the chains
+    void* arena = nullptr;
     int* abort_flag = nullptr;
-    double* e_series = nullptr;
-    int64_t e_capacity = 0;
-    uint8_t* trace_acc = nullptr;
-    double* trace_de = nullptr;
-    int64_t trace_cap = 0;
-    double* e_partial = nullptr;  // [nb]
-    EnergyAux* aux = nullptr;
-    double* e_state = nullptr;    // running energy
-    double* de_group = nullptr;   // [de_capacity] group energy changes of one launch
-    double* sweep_tot = nullptr;  // [max_launch_sweeps]
-    int64_t de_capacity = 0;
-    unsigned long long* rdf_counts = nullptr;
-    unsigned long long* rdf_centres = nullptr;
     ChainDesc* d_desc = nullptr;
-    int32_t* d_wgmap = nullptr;
-    int32_t wgmap_len = 0;
-    // host staging
-    ChainDesc desc{};
+    int2* d_wgmap = nullptr;
+    BlockItem* d_eitems = nullptr;   // energy re-sum blocks
+    int n_eitems = 0;
+    BlockItem* d_ritems = nullptr;   // g(r) blocks
+    int n_ritems = 0;
+    size_t rdf_lds = 0;
     // sweep-kernel timing (record_timing)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
     std::vector<int64_t> ev_sweeps;
     int64_t t_launches = 0, t_sweeps = 0;
     double t_ms = 0.0;
+    int64_t last_launch_sweeps = 0;
 };
 
 namespace {
@@ -173,13 +199,16 @@ void drop_events(mc_handle* h) {
 
 void free_all(mc_handle* h) {
     drop_events(h);
-    void* bufs[] = {h->pos, h->half, h->charge, h->wall_a, h->d_type, h->rec, h->stats,
-                    h->abort_flag, h->e_series, h->trace_acc, h->trace_de, h->e_partial, h->aux,
-                    h->e_state, h->de_group, h->sweep_tot, h->rdf_counts, h->rdf_centres,
-                    h->d_desc, h->d_wgmap};
-    for (void* b : bufs)
-        if (b) (void)hipFree(b);
+    for (Chain& c : h->chains) {
+        if (c.e_series) (void)hipFree(c.e_series);
+        if (c.de_group) (void)hipFree(c.de_group);
+        c.e_series = nullptr;
+        c.de_group = nullptr;
+    }
+    if (h->arena) (void)hipFree(h->arena);
+    h->arena = nullptr;
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    h->stream = nullptr;
 }
 
 // Checks the device abort word and the stream; marks the handle failed on error.
@@ -233,70 +262,243 @@ bool find_overlap(int n, const double* x, const double* sigma, double smax, int*
     return false;
 }
 
-// The descriptor is read by running kernels: drain the stream, then copy.
-int upload_desc(mc_handle* h) {
-    HIPCHECK(h, hipStreamSynchronize(h->stream));
-    HIPCHECK(h, hipMemcpy(h->d_desc, &h->desc, sizeof(ChainDesc), hipMemcpyHostToDevice));
+// Host-side validation of one chain's inputs (before any device work).
+int validate_chain(const mc_chain_spec& sp, const mc_options& opt, const std::string& who) {
+    const int32_t n = sp.n;
+    if (n < 1 || n > (1 << 24)) return fail(nullptr, MC_E_ARG, who + "n out of range [1, 2^24]");
+    if (!sp.charges || !sp.diameters || !sp.positions) return fail(nullptr, MC_E_ARG, who + "null input array");
+    if (!is_finite(sp.radius) || sp.radius <= 0) return fail(nullptr, MC_E_ARG, who + "radius must be finite and > 0");
+    if (!is_finite(sp.l_B) || sp.l_B < 0) return fail(nullptr, MC_E_ARG, who + "l_B must be finite and >= 0");
+    if (!is_finite(sp.max_disp) || sp.max_disp < 0)
+        return fail(nullptr, MC_E_ARG, who + "max_disp must be >= 0 (0 = the options' value)");
+    double qsum = 0, qabs = 0, smax = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!is_finite(sp.charges[i]) || !is_finite(sp.diameters[i]) || sp.diameters[i] <= 0)
+            return fail(nullptr, MC_E_ARG, who + "charges must be finite and diameters finite and > 0");
+        for (int k = 0; k < 3; ++k)
+            if (!is_finite(sp.positions[3 * i + k])) return fail(nullptr, MC_E_ARG, who + "non-finite position");
+        qsum += sp.charges[i];
+        qabs += std::fabs(sp.charges[i]);
+        smax = std::max(smax, sp.diameters[i]);
+    }
+    if (std::fabs(qsum) > 1e-9 * std::max(qabs, 1.0))
+        return fail(nullptr, MC_E_NOT_NEUTRAL, who + "sum of charges is not zero");
+    for (int i = 0; i < n; ++i) {
+        const double* x = sp.positions + 3 * i;
+        const double a = sp.radius - 0.5 * sp.diameters[i];
+        if (a < 0 || x[0] * x[0] + x[1] * x[1] + x[2] * x[2] > a * a)
+            return fail(nullptr, MC_E_WALL, who + "ion " + std::to_string(i) + " crosses the wall");
+    }
+    int oa = -1, ob = -1;
+    if (find_overlap(n, sp.positions, sp.diameters, smax, &oa, &ob))
+        return fail(nullptr, MC_E_OVERLAP,
+                    who + "ions " + std::to_string(oa) + " and " + std::to_string(ob) + " overlap");
+    // species: distinct (q, sigma)
+    std::vector<std::pair<double, double>> sp_list;
+    for (int i = 0; i < n; ++i) {
+        auto key = std::make_pair(sp.charges[i], sp.diameters[i]);
+        if (std::find(sp_list.begin(), sp_list.end(), key) == sp_list.end()) {
+            sp_list.push_back(key);
+            if (sp_list.size() > 8) return fail(nullptr, MC_E_ARG, who + "more than 8 species");
+        }
+    }
+    if (sizeof(unsigned int) * sp_list.size() * sp_list.size() * (size_t)opt.rdf_bins > 48 * 1024)
+        return fail(nullptr, MC_E_ARG, who + "species^2 * rdf_bins histogram does not fit in 48 KiB of LDS");
     return MC_OK;
 }
 
-int ensure_series(mc_handle* h, int64_t need) {
-    if (need <= h->e_capacity) return MC_OK;
-    int64_t cap = std::max<int64_t>(need, std::max<int64_t>(1024, 2 * h->e_capacity));
+// Fills the host side of a chain from its (validated) spec.
+void setup_chain(Chain& c, const mc_chain_spec& sp, const mc_options& opt) {
+    const int32_t n = sp.n;
+    c.n = n;
+    c.nb = (n + kGroup - 1) / kGroup;
+    c.npad = c.nb * kGroup;
+    c.R = sp.radius;
+    c.lB = sp.l_B;
+    c.D = 2.0 * (sp.max_disp > 0 ? sp.max_disp : opt.max_disp);
+    c.chain_id = sp.chain_id;
+    c.sigma0 = sp.diameters[0];
+    c.uniform_sigma = true;
+    for (int i = 1; i < n; ++i)
+        if (sp.diameters[i] != sp.diameters[0]) c.uniform_sigma = false;
+    // species: decreasing charge, then increasing diameter
+    c.species.clear();
+    for (int i = 0; i < n; ++i) {
+        auto key = std::make_pair(sp.charges[i], sp.diameters[i]);
+        if (std::find(c.species.begin(), c.species.end(), key) == c.species.end()) c.species.push_back(key);
+    }
+    std::sort(c.species.begin(), c.species.end(), [](const auto& a, const auto& b) {
+        return a.first != b.first ? a.first > b.first : a.second < b.second;
+    });
+    c.type.assign(c.npad, -1);
+    c.n_of_type.assign(c.species.size(), 0);
+    for (int i = 0; i < n; ++i) {
+        auto it = std::find(c.species.begin(), c.species.end(), std::make_pair(sp.charges[i], sp.diameters[i]));
+        c.type[i] = (int32_t)(it - c.species.begin());
+        c.n_of_type[c.type[i]] += 1;
+    }
+    c.band = opt.band >= 0 ? opt.band : 2;
+    c.band = std::min(c.band, std::min(kMaxBand, c.nb - 1));
+    c.trace_cap = opt.trace_moves;
+}
+
+// Sub-allocation of one device arena (256-byte aligned pieces).
+struct ArenaPlan {
+    size_t size = 0;
+    std::vector<std::pair<void**, size_t>> items;  // (where the pointer goes, offset)
+    template <typename P>
+    void add(P** where, size_t bytes) {
+        size = (size + 255) & ~(size_t)255;
+        items.emplace_back((void**)where, size);
+        size += bytes ? bytes : 16;
+    }
+    void assign(void* base) {
+        for (auto& it : items) *it.first = (char*)base + it.second;
+    }
+};
+
+double chain_cost(const mc_handle* h, const Chain& c, int w) {
+    return h->model_a * c.nb + h->model_b * (double)c.nb * c.nb / std::max(1, w);
+}
+
+// Workgroups per chain: water filling of the budget on the cost model
+// (each step gives one more workgroup to the chain that would finish last),
+// then the grid order: chains' workgroups sorted by per-workgroup work, the
+// heaviest half placed in order and the lightest half after it in reverse,
+// so that grid positions i and i + W/2 pair heavy with light.
+void plan_schedule(mc_handle* h, std::vector<int>& wg, std::vector<int2>& map) {
+    const int nc = (int)h->chains.size();
+    wg.assign(nc, 1);
+    int used = nc;
+    using Item = std::pair<double, int>;
+    std::priority_queue<Item> pq;
+    for (int k = 0; k < nc; ++k) pq.emplace(chain_cost(h, h->chains[k], 1), k);
+    while (!pq.empty() && used < h->wg_budget) {
+        const int k = pq.top().second;
+        pq.pop();
+        const Chain& c = h->chains[k];
+        if (wg[k] >= c.nb) continue;  // cannot use more workgroups than groups
+        wg[k] += 1;
+        used += 1;
+        pq.emplace(chain_cost(h, c, wg[k]), k);
+    }
+    std::vector<std::pair<double, int2>> per;  // (work per workgroup, (chain, index))
+    for (int k = 0; k < nc; ++k) {
+        const Chain& c = h->chains[k];
+        const double work = (double)c.nb * c.nb / wg[k];
+        for (int j = 0; j < wg[k]; ++j) per.emplace_back(work, make_int2(k, j));
+    }
+    std::stable_sort(per.begin(), per.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    const int W = (int)per.size();
+    map.assign(W, make_int2(0, 0));
+    const int half = (W + 1) / 2;
+    for (int q = 0; q < W; ++q) map[q < half ? q : W - 1 - (q - half)] = per[q].second;
+}
+
+// Fills every chain's descriptor from the host state.
+void fill_desc(mc_handle* h) {
+    for (Chain& c : h->chains) {
+        ChainDesc& d = c.desc;
+        d.n = c.n;
+        d.nb = c.nb;
+        d.band = c.band;
+        d.wg_count = c.wg;
+        d.npad = c.npad;
+        d.chain_id = c.chain_id;
+        d.lB = c.lB;
+        d.D = c.D;
+        d.half_uniform = 0.5 * c.sigma0;
+        d.pos = c.pos;
+        d.charge = c.charge;
+        d.half = c.half;
+        d.wall_a = c.wall_a;
+        d.rec = c.rec;
+        d.stats = c.stats;
+        d.de_group = c.de_group;
+        d.trace_acc = c.trace_acc;
+        d.trace_de = c.trace_de;
+        d.trace_cap = c.trace_cap;
+        d.clk = c.clk;
+        d.e_partial = c.e_partial;
+        d.aux = c.aux;
+        d.e_state = c.e_state;
+        d.sweep_tot = c.sweep_tot;
+        d.e_series = c.e_series;
+        d.e_capacity = c.e_capacity;
+        d.type = c.d_type;
+        d.ntypes = (int32_t)c.species.size();
+        d.rdf_rc = c.R - h->opt.rdf_rmax;
+        d.rdf_counts = c.rdf_counts;
+        d.rdf_centres = c.rdf_centres;
+    }
+}
+
+// The descriptors are read by running kernels: drain the stream, then copy.
+int upload_desc(mc_handle* h) {
+    fill_desc(h);
+    std::vector<ChainDesc> v;
+    v.reserve(h->chains.size());
+    for (const Chain& c : h->chains) v.push_back(c.desc);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    HIPCHECK(h, hipMemcpy(h->d_desc, v.data(), sizeof(ChainDesc) * v.size(), hipMemcpyHostToDevice));
+    return MC_OK;
+}
+
+// Applies a workgroup count per chain: new grid map and descriptors.
+int apply_schedule(mc_handle* h, const std::vector<int>& wg, const std::vector<int2>& map) {
+    for (size_t k = 0; k < h->chains.size(); ++k) h->chains[k].wg = wg[k];
+    h->wg_total = (int)map.size();
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    HIPCHECK(h, hipMemcpy(h->d_wgmap, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice));
+    return upload_desc(h);
+}
+
+int grow_buffer(mc_handle* h, double** buf, int64_t* capacity, int64_t need, bool keep) {
+    if (need <= *capacity) return MC_OK;
+    const int64_t cap = std::max<int64_t>(need, std::max<int64_t>(1024, 2 * *capacity));
     double* nb = nullptr;
     int rc = dalloc(h, &nb, sizeof(double) * cap);
     if (rc) return rc;
-    if (h->e_series) {
-        HIPCHECK(h, hipMemcpyAsync(nb, h->e_series, sizeof(double) * h->e_capacity,
-                                   hipMemcpyDeviceToDevice, h->stream));
-        HIPCHECK(h, hipStreamSynchronize(h->stream));
-        (void)hipFree(h->e_series);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    if (*buf) {
+        if (keep) HIPCHECK(h, hipMemcpy(nb, *buf, sizeof(double) * *capacity, hipMemcpyDeviceToDevice));
+        (void)hipFree(*buf);
     }
-    h->e_series = nb;
-    h->e_capacity = cap;
+    *buf = nb;
+    *capacity = cap;
     return MC_OK;
 }
 
 int launch_energy(mc_handle* h, int reset, int record_drift) {
-    const int nparts = (h->nb + 1) / 2;
     const int parity = (int)((h->sweeps - 1) & 1);
-    const size_t t4 = h->fp64 ? sizeof(double4) : sizeof(float4);
-    const void* p = (const char*)h->pos + (size_t)parity * h->npad * t4;
     if (h->fp64)
-        hipLaunchKernelGGL(energy_partial_kernel<double>, dim3(nparts), dim3(256), 0, h->stream,
-                           (const double4*)p, (const double*)h->charge, h->nb, h->e_partial);
+        hipLaunchKernelGGL(energy_partial_kernel<double>, dim3(h->n_eitems), dim3(256), 0, h->stream,
+                           h->d_desc, h->d_eitems, parity);
     else
-        hipLaunchKernelGGL(energy_partial_kernel<float>, dim3(nparts), dim3(256), 0, h->stream,
-                           (const float4*)p, (const float*)h->charge, h->nb, h->e_partial);
+        hipLaunchKernelGGL(energy_partial_kernel<float>, dim3(h->n_eitems), dim3(256), 0, h->stream,
+                           h->d_desc, h->d_eitems, parity);
     HIPCHECK(h, hipGetLastError());
-    hipLaunchKernelGGL(energy_finalize_kernel, dim3(1), dim3(64), 0, h->stream, h->e_partial, nparts,
-                       h->lB, h->e_state, h->aux, reset, record_drift);
+    hipLaunchKernelGGL(energy_finalize_kernel, dim3((unsigned)h->chains.size()), dim3(64), 0, h->stream,
+                       h->d_desc, reset, record_drift);
     HIPCHECK(h, hipGetLastError());
     return MC_OK;
 }
 
 int launch_rdf(mc_handle* h) {
-    const int nt = (int)h->species.size();
     const int bins = h->opt.rdf_bins;
     const double rmax = h->opt.rdf_rmax;
     const double dr = rmax / (double)bins;
-    const double rc = h->R - rmax;
-    const size_t lds = sizeof(unsigned int) * (size_t)nt * nt * bins;
     const int parity = (int)((h->sweeps - 1) & 1);
-    const size_t t4 = h->fp64 ? sizeof(double4) : sizeof(float4);
-    const void* p = (const char*)h->pos + (size_t)parity * h->npad * t4;
     if (h->fp64)
-        hipLaunchKernelGGL(rdf_kernel<double>, dim3(h->nb), dim3(256), lds, h->stream, (const double4*)p,
-                           h->d_type, h->n, h->nb, nt, rc, rmax, dr, bins, h->rdf_counts, h->rdf_centres);
+        hipLaunchKernelGGL(rdf_kernel<double>, dim3(h->n_ritems), dim3(256), h->rdf_lds, h->stream, h->d_desc,
+                           h->d_ritems, parity, rmax, dr, bins);
     else
-        hipLaunchKernelGGL(rdf_kernel<float>, dim3(h->nb), dim3(256), lds, h->stream, (const float4*)p,
-                           h->d_type, h->n, h->nb, nt, rc, rmax, dr, bins, h->rdf_counts, h->rdf_centres);
+        hipLaunchKernelGGL(rdf_kernel<float>, dim3(h->n_ritems), dim3(256), h->rdf_lds, h->stream, h->d_desc,
+                           h->d_ritems, parity, rmax, dr, bins);
     HIPCHECK(h, hipGetLastError());
     h->rdf_samples += 1;
     return MC_OK;
 }
-
-constexpr int64_t kMaxLaunchSweeps = 4096;
 
 int launch_sweeps(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
     if (n_sweeps <= 0) return MC_OK;
@@ -305,22 +507,20 @@ int launch_sweeps(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
         if (rc) return rc;
         return launch_sweeps(h, n_sweeps - kMaxLaunchSweeps, seed);
     }
-    int rc = ensure_series(h, h->sweeps + n_sweeps);
-    if (rc) return rc;
-    const int64_t ngroups = n_sweeps * (int64_t)h->nb;
-    if (ngroups > h->de_capacity) {
-        HIPCHECK(h, hipStreamSynchronize(h->stream));
-        if (h->de_group) (void)hipFree(h->de_group);
-        h->de_group = nullptr;
-        h->de_capacity = 0;
-        if ((rc = dalloc(h, &h->de_group, sizeof(double) * ngroups))) return rc;
-        h->de_capacity = ngroups;
-        h->desc.de_group = h->de_group;
-        if ((rc = upload_desc(h))) return rc;
+    bool changed = false;
+    for (Chain& c : h->chains) {
+        const int64_t s_cap = c.e_capacity, d_cap = c.de_capacity;
+        int rc = grow_buffer(h, &c.e_series, &c.e_capacity, h->sweeps + n_sweeps, true);
+        if (!rc) rc = grow_buffer(h, &c.de_group, &c.de_capacity, n_sweeps * (int64_t)c.nb, false);
+        if (rc) return rc;
+        changed |= s_cap != c.e_capacity || d_cap != c.de_capacity;
     }
-    if (h->desc.seed != seed) {
-        h->desc.seed = seed;
-        if ((rc = upload_desc(h))) return rc;
+    bool reseed = false;
+    for (Chain& c : h->chains) reseed |= c.desc.seed != seed;
+    if (changed || reseed) {
+        for (Chain& c : h->chains) c.desc.seed = seed;
+        int rc = upload_desc(h);
+        if (rc) return rc;
     }
     SweepFn fn = pick_sweep(h->fp64, h->waves, h->uniform_sigma);
     Ctl ctl;
@@ -329,7 +529,7 @@ int launch_sweeps(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
     uint32_t s0 = (uint32_t)h->sweeps;
     int32_t ns = (int32_t)n_sweeps;
     const ChainDesc* dd = h->d_desc;
-    const int32_t* wm = h->d_wgmap;
+    const int2* wm = h->d_wgmap;
     void* args[] = {(void*)&dd, (void*)&wm, (void*)&s0, (void*)&ns, (void*)&ctl};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->opt.record_timing) {
@@ -337,18 +537,427 @@ int launch_sweeps(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
         HIPCHECK(h, hipEventCreate(&e1));
         HIPCHECK(h, hipEventRecord(e0, h->stream));
     }
-    HIPCHECK(h, hipLaunchCooperativeKernel((const void*)fn, dim3(h->wg), dim3(64 * h->waves), args, 0,
+    HIPCHECK(h, hipLaunchCooperativeKernel((const void*)fn, dim3(h->wg_total), dim3(64 * h->waves), args, 0,
                                            h->stream));
     if (h->opt.record_timing) {
         HIPCHECK(h, hipEventRecord(e1, h->stream));
         h->ev_pending.emplace_back(e0, e1);
         h->ev_sweeps.push_back(n_sweeps);
     }
-    hipLaunchKernelGGL(energy_scan_kernel, dim3(1), dim3(256), 0, h->stream, h->de_group, h->nb,
-                       (int32_t)n_sweeps, (int64_t)h->sweeps, h->sweep_tot, h->e_state, h->e_series,
-                       h->e_capacity);
+    hipLaunchKernelGGL(energy_scan_kernel, dim3((unsigned)h->chains.size()), dim3(256), 0, h->stream, h->d_desc,
+                       (int32_t)n_sweeps, (int64_t)h->sweeps);
     HIPCHECK(h, hipGetLastError());
     h->sweeps += n_sweeps;
+    h->last_launch_sweeps = n_sweeps;
+    return MC_OK;
+}
+
+int sweep_all(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
+    if (n_sweeps < 0 || h->sweeps + n_sweeps > (int64_t)UINT32_MAX)
+        return fail(h, MC_E_ARG, "n_sweeps out of range");
+    int64_t left = n_sweeps;
+    while (left > 0) {
+        int64_t step = left;
+        const int re = h->opt.resum_every, rd = h->opt.rdf_every;
+        if (re > 0) step = std::min<int64_t>(step, re - h->sweeps % re);
+        if (rd > 0) step = std::min<int64_t>(step, rd - h->sweeps % rd);
+        int rc = launch_sweeps(h, step, seed);
+        if (rc) return rc;
+        left -= step;
+        if (re > 0 && h->sweeps % re == 0 && (rc = launch_energy(h, 1, 1))) return rc;
+        if (rd > 0 && h->sweeps % rd == 0 && (rc = launch_rdf(h))) return rc;
+    }
+    return MC_OK;
+}
+
+// Builds a handle from validated chain specs.
+int create_handle(int32_t n_chains, const mc_chain_spec* specs, const mc_options& opt, mc_handle** out) {
+    mc_handle* h = new (std::nothrow) mc_handle();
+    if (!h) return fail(nullptr, MC_E_OOM, "host allocation failed");
+    std::string derr;
+    if (!device_info(h->dev, derr)) {
+        delete h;
+        return fail(nullptr, MC_E_DEVICE, derr);
+    }
+    h->opt = opt;
+    h->fp64 = opt.precision == MC_FP64;
+    h->waves = opt.waves ? opt.waves : 4;
+    h->chains.resize(n_chains);
+    h->uniform_sigma = true;
+    for (int k = 0; k < n_chains; ++k) {
+        setup_chain(h->chains[k], specs[k], opt);
+        h->uniform_sigma = h->uniform_sigma && h->chains[k].uniform_sigma;
+    }
+
+    int rc = MC_OK;
+    auto bail = [&](int code) {
+        if (h->stream) (void)hipStreamSynchronize(h->stream);
+        std::string m = h->err;
+        free_all(h);
+        delete h;
+        g_create_error = m;
+        return code;
+    };
+    if (opt.hip_stream) {
+        h->stream = (hipStream_t)opt.hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+            h->err = "hipStreamCreate failed";
+            return bail(MC_E_DEVICE);
+        }
+        h->own_stream = true;
+    }
+
+    // co-residency of the sweep kernel: every workgroup of the cooperative
+    // grid must be resident at once
+    SweepFn fn = pick_sweep(h->fp64, h->waves, h->uniform_sigma);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, 64 * h->waves, 0) != hipSuccess ||
+        per_cu < 1) {
+        h->err = "occupancy query failed for the sweep kernel";
+        return bail(MC_E_DEVICE);
+    }
+    // The occupancy query has been seen to over-promise for workgroups with
+    // more than 64 KiB of LDS: such kernels get one workgroup per CU.
+    // Kernels that spill to scratch have been seen to run fewer workgroups at
+    // once than the query reports: they also get one workgroup per CU.
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, (const void*)fn) == hipSuccess &&
+        (fa.sharedSizeBytes > 64 * 1024 || fa.localSizeBytes > 0))
+        per_cu = 1;
+    h->cap = per_cu * h->dev.cus;
+    if (n_chains > h->cap) {
+        h->err = "more chains (" + std::to_string(n_chains) + ") than co-resident workgroups (" +
+                 std::to_string(h->cap) + ")";
+        return bail(MC_E_ARG);
+    }
+    h->wg_budget = opt.workgroups > 0 ? std::max(n_chains, std::min(opt.workgroups, h->cap)) : h->cap;
+
+    // device memory: one arena for the fixed-size buffers
+    const size_t t4 = h->fp64 ? sizeof(double4) : sizeof(float4);
+    const size_t t1 = h->fp64 ? sizeof(double) : sizeof(float);
+    ArenaPlan plan;
+    plan.add(&h->abort_flag, sizeof(int));
+    plan.add(&h->d_desc, sizeof(ChainDesc) * n_chains);
+    plan.add(&h->d_wgmap, sizeof(int2) * h->cap);
+    int n_e = 0, n_r = 0;
+    size_t max_hist = 0;
+    for (Chain& c : h->chains) {
+        n_e += (c.nb + 1) / 2;
+        n_r += c.nb;
+        const size_t nt = c.species.size();
+        max_hist = std::max(max_hist, nt * nt * (size_t)opt.rdf_bins);
+    }
+    h->n_eitems = n_e;
+    h->n_ritems = n_r;
+    h->rdf_lds = sizeof(unsigned int) * max_hist;
+    plan.add(&h->d_eitems, sizeof(BlockItem) * n_e);
+    plan.add(&h->d_ritems, sizeof(BlockItem) * n_r);
+    for (Chain& c : h->chains) {
+        const size_t nt = c.species.size();
+        plan.add(&c.pos, 2 * t4 * c.npad);
+        plan.add(&c.half, t1 * c.npad);
+        plan.add(&c.charge, t1 * c.npad);
+        plan.add(&c.wall_a, sizeof(double) * c.npad);
+        plan.add(&c.d_type, sizeof(int32_t) * c.npad);
+        plan.add(&c.rec, sizeof(GroupRec) * kRing);
+        plan.add(&c.stats, sizeof(unsigned long long) * ST_N);
+        plan.add(&c.clk, sizeof(unsigned long long) * 2);
+        plan.add(&c.e_partial, sizeof(double) * ((c.nb + 1) / 2));
+        plan.add(&c.aux, sizeof(EnergyAux));
+        plan.add(&c.e_state, sizeof(double));
+        plan.add(&c.sweep_tot, sizeof(double) * kMaxLaunchSweeps);
+        plan.add(&c.rdf_counts, sizeof(unsigned long long) * nt * nt * opt.rdf_bins);
+        plan.add(&c.rdf_centres, sizeof(unsigned long long) * nt);
+        if (c.trace_cap > 0) {
+            plan.add(&c.trace_acc, (size_t)c.trace_cap);
+            plan.add(&c.trace_de, sizeof(double) * c.trace_cap);
+        }
+    }
+    if ((rc = dalloc(h, &h->arena, plan.size))) return bail(rc);
+    plan.assign(h->arena);
+    // zero everything once (the handle's stream is non-blocking: drain it
+    // before the synchronous uploads below)
+    if (hipMemsetAsync(h->arena, 0, plan.size, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+        h->err = "clearing device memory failed";
+        return bail(MC_E_DEVICE);
+    }
+
+    // host images and uploads, chain by chain
+    std::vector<BlockItem> eitems, ritems;
+    for (int k = 0; k < n_chains; ++k) {
+        Chain& c = h->chains[k];
+        const mc_chain_spec& sp = specs[k];
+        for (int p = 0; p < (c.nb + 1) / 2; ++p) eitems.push_back(BlockItem{k, p});
+        for (int r = 0; r < c.nb; ++r) ritems.push_back(BlockItem{k, r});
+        // positions carry the version tag of the sweep that produced them;
+        // the initial state is the result of virtual sweeps -2 (parity 0)
+        // and -1 (parity 1)
+        std::vector<char> hpos(2 * t4 * c.npad), hhalf(t1 * c.npad), hq(t1 * c.npad);
+        std::vector<double> hwall(c.npad, 0.0);
+        for (int i = 0; i < c.npad; ++i) {
+            double x, y, z, qq, hh;
+            if (i < c.n) {
+                x = sp.positions[3 * i];
+                y = sp.positions[3 * i + 1];
+                z = sp.positions[3 * i + 2];
+                qq = sp.charges[i];
+                hh = 0.5 * sp.diameters[i];
+                hwall[i] = c.R - 0.5 * sp.diameters[i];
+            } else {
+                // inert padding ion: no charge, no size, far from everything and from each other
+                x = 1.0e6 * (double)(i - c.n + 1);
+                y = -2.0e6;
+                z = 3.0e6;
+                qq = 0.0;
+                hh = 0.0;
+            }
+            for (int par = 0; par < 2; ++par) {
+                const uint32_t ver = par == 0 ? 0xFFFFFFFEu : 0xFFFFFFFFu;
+                char* dst = &hpos[t4 * ((size_t)par * c.npad + i)];
+                if (h->fp64) {
+                    struct { double x, y, z; uint32_t ver, pad; } r{x, y, z, ver, 0u};
+                    std::memcpy(dst, &r, t4);
+                } else {
+                    struct { float x, y, z; uint32_t ver; } r{(float)x, (float)y, (float)z, ver};
+                    std::memcpy(dst, &r, t4);
+                }
+            }
+            if (h->fp64) {
+                std::memcpy(&hhalf[t1 * i], &hh, t1);
+                std::memcpy(&hq[t1 * i], &qq, t1);
+            } else {
+                float hf = (float)hh, qf = (float)qq;
+                std::memcpy(&hhalf[t1 * i], &hf, t1);
+                std::memcpy(&hq[t1 * i], &qf, t1);
+            }
+        }
+        std::vector<GroupRec> hrec(kRing);
+        for (int q = 0; q < kRing; ++q) {
+            const int64_t g = (int64_t)q - kRing;  // virtual groups -kRing..-1: decided, nothing accepted
+            hrec[(size_t)(g & (kRing - 1))] = GroupRec{(uint32_t)(g + 1), 0u, 0ull};
+        }
+        hipError_t e = hipSuccess;
+        if ((e = hipMemcpy(c.pos, hpos.data(), hpos.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c.half, hhalf.data(), hhalf.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c.charge, hq.data(), hq.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c.wall_a, hwall.data(), sizeof(double) * c.npad, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c.d_type, c.type.data(), sizeof(int32_t) * c.npad, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c.rec, hrec.data(), sizeof(GroupRec) * kRing, hipMemcpyHostToDevice)) != hipSuccess) {
+            h->err = std::string("upload failed: ") + hipGetErrorString(e);
+            return bail(MC_E_DEVICE);
+        }
+        if (c.trace_cap) {
+            std::vector<uint8_t> ff((size_t)c.trace_cap, 0xFF);
+            if ((e = hipMemcpy(c.trace_acc, ff.data(), ff.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+                h->err = std::string("upload failed: ") + hipGetErrorString(e);
+                return bail(MC_E_DEVICE);
+            }
+        }
+    }
+    {
+        hipError_t e = hipSuccess;
+        if ((e = hipMemcpy(h->d_eitems, eitems.data(), sizeof(BlockItem) * eitems.size(), hipMemcpyHostToDevice)) !=
+                hipSuccess ||
+            (e = hipMemcpy(h->d_ritems, ritems.data(), sizeof(BlockItem) * ritems.size(), hipMemcpyHostToDevice)) !=
+                hipSuccess) {
+            h->err = std::string("upload failed: ") + hipGetErrorString(e);
+            return bail(MC_E_DEVICE);
+        }
+    }
+    for (Chain& c : h->chains) {
+        if ((rc = grow_buffer(h, &c.e_series, &c.e_capacity, 1024, false))) return bail(rc);
+    }
+    std::vector<int> wg;
+    std::vector<int2> map;
+    plan_schedule(h, wg, map);
+    if ((rc = apply_schedule(h, wg, map))) return bail(rc);
+    // initial energy: re-sum into the running energy
+    if ((rc = launch_energy(h, 1, 0))) return bail(rc);
+    if ((rc = sync_check(h))) return bail(rc);
+    *out = h;
+    return MC_OK;
+}
+
+int check_options(const mc_options& opt) {
+    if (opt.precision != MC_FP64 && opt.precision != MC_FP32_ACC64)
+        return fail(nullptr, MC_E_ARG, "unknown precision");
+    if (!is_finite(opt.max_disp) || opt.max_disp <= 0) return fail(nullptr, MC_E_ARG, "max_disp must be > 0");
+    if (opt.resum_every < 0 || opt.rdf_every < 0) return fail(nullptr, MC_E_ARG, "negative interval");
+    if (opt.rdf_bins < 1 || opt.rdf_bins > 4096 || !is_finite(opt.rdf_rmax) || opt.rdf_rmax <= 0)
+        return fail(nullptr, MC_E_ARG, "rdf_bins must be in [1, 4096] and rdf_rmax > 0");
+    if (opt.band < -1 || opt.band > kMaxBand) return fail(nullptr, MC_E_ARG, "band out of range");
+    if (opt.waves != 0 && opt.waves != 4 && opt.waves != 8) return fail(nullptr, MC_E_ARG, "waves must be 0, 4 or 8");
+    if (opt.workgroups < 0 || opt.trace_moves < 0) return fail(nullptr, MC_E_ARG, "negative count");
+    if (!is_finite(opt.wait_timeout_s) || opt.wait_timeout_s <= 0) return fail(nullptr, MC_E_ARG, "bad wait_timeout_s");
+    return MC_OK;
+}
+
+Chain* get_chain(mc_handle* h, int32_t c) {
+    if (!h || c < 0 || c >= (int32_t)h->chains.size()) return nullptr;
+    return &h->chains[c];
+}
+
+int chain_energy(mc_handle* h, int32_t ci, double* e_running, double* e_exact) {
+    Chain* c = get_chain(h, ci);
+    if (!c || !e_running) return h ? fail(h, MC_E_ARG, "bad chain index or null output") : MC_E_ARG;
+    int rc = sync_check(h);
+    if (rc) return rc;
+    HIPCHECK(h, hipMemcpy(e_running, c->e_state, sizeof(double), hipMemcpyDeviceToHost));
+    if (e_exact) {
+        if ((rc = launch_energy(h, 0, 0))) return rc;
+        if ((rc = sync_check(h))) return rc;
+        EnergyAux a;
+        HIPCHECK(h, hipMemcpy(&a, c->aux, sizeof(EnergyAux), hipMemcpyDeviceToHost));
+        *e_exact = a.e_resum;
+    }
+    return MC_OK;
+}
+
+int chain_rdf(mc_handle* h, int32_t ci, int32_t bins, double* g, uint64_t* counts, uint64_t* centres,
+              int64_t* n_samples) {
+    Chain* c = get_chain(h, ci);
+    if (!c) return h ? fail(h, MC_E_ARG, "bad chain index") : MC_E_ARG;
+    if (bins != h->opt.rdf_bins) return fail(h, MC_E_ARG, "bins differs from the handle's rdf_bins");
+    int rc = sync_check(h);
+    if (rc) return rc;
+    const size_t nt = c->species.size();
+    const size_t nh = nt * nt * (size_t)bins;
+    std::vector<unsigned long long> cnt(nh), ce(nt);
+    HIPCHECK(h, hipMemcpy(cnt.data(), c->rdf_counts, sizeof(unsigned long long) * nh, hipMemcpyDeviceToHost));
+    HIPCHECK(h, hipMemcpy(ce.data(), c->rdf_centres, sizeof(unsigned long long) * nt, hipMemcpyDeviceToHost));
+    if (counts)
+        for (size_t k = 0; k < nh; ++k) counts[k] = cnt[k];
+    if (centres)
+        for (size_t k = 0; k < nt; ++k) centres[k] = ce[k];
+    if (n_samples) *n_samples = h->rdf_samples;
+    if (g) {
+        const double rmax = h->opt.rdf_rmax, dr = rmax / (double)bins;
+        const double pi = 3.14159265358979323846;
+        for (size_t a = 0; a < nt; ++a)
+            for (size_t b = 0; b < nt; ++b) {
+                const double rb = c->R - 0.5 * c->species[b].second;
+                const double vb = 4.0 / 3.0 * pi * rb * rb * rb;
+                const double nbd = (double)(c->n_of_type[b] - (a == b ? 1 : 0)) / vb;
+                for (int k = 0; k < bins; ++k) {
+                    const double r0 = k * dr, r1 = (k + 1) * dr;
+                    const double vk = 4.0 / 3.0 * pi * (r1 * r1 * r1 - r0 * r0 * r0);
+                    const double den = (double)ce[a] * nbd * vk;
+                    g[(a * nt + b) * bins + k] = den > 0 ? (double)cnt[(a * nt + b) * bins + k] / den : 0.0;
+                }
+            }
+    }
+    return MC_OK;
+}
+
+int chain_species(const mc_handle* h, int32_t ci, int32_t* ntypes, double* q, double* s) {
+    if (!h || ci < 0 || ci >= (int32_t)h->chains.size()) return MC_E_ARG;
+    const Chain& c = h->chains[ci];
+    if (ntypes) *ntypes = (int32_t)c.species.size();
+    for (size_t k = 0; k < c.species.size(); ++k) {
+        if (q) q[k] = c.species[k].first;
+        if (s) s[k] = c.species[k].second;
+    }
+    return MC_OK;
+}
+
+int chain_positions(mc_handle* h, int32_t ci, double* xyz) {
+    Chain* c = get_chain(h, ci);
+    if (!c || !xyz) return h ? fail(h, MC_E_ARG, "bad chain index or null output") : MC_E_ARG;
+    int rc = sync_check(h);
+    if (rc) return rc;
+    const int parity = (int)((h->sweeps - 1) & 1);
+    if (h->fp64) {
+        std::vector<double4> v(c->n);
+        HIPCHECK(h, hipMemcpy(v.data(), (double4*)c->pos + (size_t)parity * c->npad, sizeof(double4) * c->n,
+                              hipMemcpyDeviceToHost));
+        for (int i = 0; i < c->n; ++i) {
+            xyz[3 * i] = v[i].x;
+            xyz[3 * i + 1] = v[i].y;
+            xyz[3 * i + 2] = v[i].z;
+        }
+    } else {
+        std::vector<float4> v(c->n);
+        HIPCHECK(h, hipMemcpy(v.data(), (float4*)c->pos + (size_t)parity * c->npad, sizeof(float4) * c->n,
+                              hipMemcpyDeviceToHost));
+        for (int i = 0; i < c->n; ++i) {
+            xyz[3 * i] = v[i].x;
+            xyz[3 * i + 1] = v[i].y;
+            xyz[3 * i + 2] = v[i].z;
+        }
+    }
+    return MC_OK;
+}
+
+int chain_trace(mc_handle* h, int32_t ci, int64_t n_moves, uint8_t* acc, double* dE) {
+    Chain* c = get_chain(h, ci);
+    if (!c) return h ? fail(h, MC_E_ARG, "bad chain index") : MC_E_ARG;
+    if (n_moves < 0 || n_moves > c->trace_cap || n_moves > h->sweeps * (int64_t)c->n)
+        return fail(h, MC_E_ARG, "n_moves exceeds the traced moves");
+    int rc = sync_check(h);
+    if (rc) return rc;
+    if (acc && n_moves) HIPCHECK(h, hipMemcpy(acc, c->trace_acc, (size_t)n_moves, hipMemcpyDeviceToHost));
+    if (dE && n_moves) HIPCHECK(h, hipMemcpy(dE, c->trace_de, sizeof(double) * n_moves, hipMemcpyDeviceToHost));
+    return MC_OK;
+}
+
+int chain_energy_series(mc_handle* h, int32_t ci, int64_t n, double* e) {
+    Chain* c = get_chain(h, ci);
+    if (!c) return h ? fail(h, MC_E_ARG, "bad chain index") : MC_E_ARG;
+    if (n < 0 || n > h->sweeps || (n && !e)) return fail(h, MC_E_ARG, "n exceeds the sweeps done");
+    int rc = sync_check(h);
+    if (rc) return rc;
+    if (n) HIPCHECK(h, hipMemcpy(e, c->e_series, sizeof(double) * n, hipMemcpyDeviceToHost));
+    return MC_OK;
+}
+
+int chain_stats(mc_handle* h, int32_t ci, mc_stats* out) {
+    Chain* c = get_chain(h, ci);
+    if (!c || !out) return h ? fail(h, MC_E_ARG, "bad chain index or null output") : MC_E_ARG;
+    int rc = sync_check(h);
+    if (rc) return rc;
+    unsigned long long st[ST_N];
+    EnergyAux a;
+    HIPCHECK(h, hipMemcpy(st, c->stats, sizeof(st), hipMemcpyDeviceToHost));
+    HIPCHECK(h, hipMemcpy(&a, c->aux, sizeof(a), hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof(*out));
+    out->sweeps = h->sweeps;
+    out->moves = (int64_t)st[ST_MOVES];
+    out->accepted = (int64_t)st[ST_ACC];
+    out->rejected_wall = (int64_t)st[ST_WALL];
+    out->rejected_overlap = (int64_t)st[ST_OVERLAP];
+    out->rejected_metropolis = (int64_t)st[ST_METRO];
+    out->fixpoint_iterations = (int64_t)st[ST_ITERS];
+    out->early_groups = (int64_t)st[ST_EARLY];
+    out->resums = (int64_t)a.n_resum;
+    out->last_drift = a.drift_last;
+    out->max_abs_drift = a.drift_max;
+    out->band = c->band;
+    out->waves = h->waves;
+    out->workgroups = c->wg;
+    return MC_OK;
+}
+
+int chain_set_max_disp(mc_handle* h, int32_t ci, double max_disp) {
+    Chain* c = get_chain(h, ci);
+    if (!c) return h ? fail(h, MC_E_ARG, "bad chain index") : MC_E_ARG;
+    if (!is_finite(max_disp) || max_disp <= 0) return fail(h, MC_E_ARG, "max_disp must be > 0");
+    c->D = 2.0 * max_disp;
+    return upload_desc(h);
+}
+
+// Device time of the last sweep launch for every chain, in milliseconds, from
+// the chain clocks (launch start to the chain's last published group).
+int last_launch_ms(mc_handle* h, std::vector<double>& ms) {
+    int rc = sync_check(h);
+    if (rc) return rc;
+    ms.assign(h->chains.size(), 0.0);
+    for (size_t k = 0; k < h->chains.size(); ++k) {
+        unsigned long long clk[2];
+        HIPCHECK(h, hipMemcpy(clk, h->chains[k].clk, sizeof(clk), hipMemcpyDeviceToHost));
+        ms[k] = clk[1] > clk[0] ? 1e3 * (double)(clk[1] - clk[0]) / h->dev.wall_clock_hz : 0.0;
+    }
     return MC_OK;
 }
 
@@ -382,307 +991,43 @@ int mc_create(int32_t n, const double* charges, const double* diameters, const d
     mc_options opt;
     mc_options_init(&opt);
     if (opt_in) opt = *opt_in;
-    if (n < 1 || n > (1 << 24)) return fail(nullptr, MC_E_ARG, "n out of range [1, 2^24]");
-    if (!charges || !diameters || !positions) return fail(nullptr, MC_E_ARG, "null input array");
-    if (!is_finite(radius) || radius <= 0) return fail(nullptr, MC_E_ARG, "radius must be finite and > 0");
-    if (!is_finite(l_B) || l_B < 0) return fail(nullptr, MC_E_ARG, "l_B must be finite and >= 0");
-    if (opt.precision != MC_FP64 && opt.precision != MC_FP32_ACC64)
-        return fail(nullptr, MC_E_ARG, "unknown precision");
-    if (!is_finite(opt.max_disp) || opt.max_disp <= 0) return fail(nullptr, MC_E_ARG, "max_disp must be > 0");
-    if (opt.resum_every < 0 || opt.rdf_every < 0) return fail(nullptr, MC_E_ARG, "negative interval");
-    if (opt.rdf_bins < 1 || opt.rdf_bins > 4096 || !is_finite(opt.rdf_rmax) || opt.rdf_rmax <= 0)
-        return fail(nullptr, MC_E_ARG, "rdf_bins must be in [1, 4096] and rdf_rmax > 0");
-    if (opt.band < -1 || opt.band > kMaxBand) return fail(nullptr, MC_E_ARG, "band out of range");
-    if (opt.waves != 0 && opt.waves != 4 && opt.waves != 8) return fail(nullptr, MC_E_ARG, "waves must be 0, 4 or 8");
-    if (opt.workgroups < 0 || opt.trace_moves < 0) return fail(nullptr, MC_E_ARG, "negative count");
-    if (!is_finite(opt.wait_timeout_s) || opt.wait_timeout_s <= 0) return fail(nullptr, MC_E_ARG, "bad wait_timeout_s");
+    int rc = check_options(opt);
+    if (rc) return rc;
+    mc_chain_spec sp;
+    std::memset(&sp, 0, sizeof(sp));
+    sp.n = n;
+    sp.charges = charges;
+    sp.diameters = diameters;
+    sp.positions = positions;
+    sp.radius = radius;
+    sp.l_B = l_B;
+    sp.max_disp = opt.max_disp;
+    sp.chain_id = opt.chain_id;
+    if ((rc = validate_chain(sp, opt, ""))) return rc;
+    return create_handle(1, &sp, opt, out);
+}
 
-    double qsum = 0, qabs = 0, smax = 0;
-    for (int i = 0; i < n; ++i) {
-        if (!is_finite(charges[i]) || !is_finite(diameters[i]) || diameters[i] <= 0)
-            return fail(nullptr, MC_E_ARG, "charges must be finite and diameters finite and > 0");
-        for (int k = 0; k < 3; ++k)
-            if (!is_finite(positions[3 * i + k])) return fail(nullptr, MC_E_ARG, "non-finite position");
-        qsum += charges[i];
-        qabs += std::fabs(charges[i]);
-        smax = std::max(smax, diameters[i]);
-    }
-    if (std::fabs(qsum) > 1e-9 * std::max(qabs, 1.0))
-        return fail(nullptr, MC_E_NOT_NEUTRAL, "sum of charges is not zero");
-    for (int i = 0; i < n; ++i) {
-        const double* x = positions + 3 * i;
-        const double a = radius - 0.5 * diameters[i];
-        if (a < 0 || x[0] * x[0] + x[1] * x[1] + x[2] * x[2] > a * a)
-            return fail(nullptr, MC_E_WALL, "ion " + std::to_string(i) + " crosses the wall");
-    }
-    int oa = -1, ob = -1;
-    if (find_overlap(n, positions, diameters, smax, &oa, &ob))
-        return fail(nullptr, MC_E_OVERLAP,
-                    "ions " + std::to_string(oa) + " and " + std::to_string(ob) + " overlap");
-
-    mc_handle* h = new (std::nothrow) mc_handle();
-    if (!h) return fail(nullptr, MC_E_OOM, "host allocation failed");
-    std::string derr;
-    if (!device_info(h->dev, derr)) {
-        delete h;
-        return fail(nullptr, MC_E_DEVICE, derr);
-    }
-    h->opt = opt;
-    h->n = n;
-    h->nb = (n + kGroup - 1) / kGroup;
-    h->npad = h->nb * kGroup;
-    h->fp64 = opt.precision == MC_FP64;
-    h->R = radius;
-    h->lB = l_B;
-    h->D = 2.0 * opt.max_disp;
-    h->q.assign(charges, charges + n);
-    h->sigma.assign(diameters, diameters + n);
-    h->uniform_sigma = true;
-    for (int i = 1; i < n; ++i)
-        if (diameters[i] != diameters[0]) h->uniform_sigma = false;
-    // species: distinct (q, sigma), decreasing charge then increasing diameter
-    for (int i = 0; i < n; ++i) {
-        auto key = std::make_pair(charges[i], diameters[i]);
-        if (std::find(h->species.begin(), h->species.end(), key) == h->species.end())
-            h->species.push_back(key);
-    }
-    if (h->species.size() > 8) {
-        delete h;
-        return fail(nullptr, MC_E_ARG, "more than 8 species");
-    }
-    if (sizeof(unsigned int) * h->species.size() * h->species.size() * (size_t)opt.rdf_bins > 48 * 1024) {
-        delete h;
-        return fail(nullptr, MC_E_ARG, "species^2 * rdf_bins histogram does not fit in 48 KiB of LDS");
-    }
-    std::sort(h->species.begin(), h->species.end(), [](const auto& a, const auto& b) {
-        return a.first != b.first ? a.first > b.first : a.second < b.second;
-    });
-    h->type.resize(h->npad, -1);
-    h->n_of_type.assign(h->species.size(), 0);
-    for (int i = 0; i < n; ++i) {
-        auto it = std::find(h->species.begin(), h->species.end(), std::make_pair(charges[i], diameters[i]));
-        h->type[i] = (int32_t)(it - h->species.begin());
-        h->n_of_type[h->type[i]] += 1;
-    }
-
-    // schedule
-    h->band = opt.band >= 0 ? opt.band : 2;
-    h->band = std::min(h->band, std::min(kMaxBand, h->nb - 1));
-    h->waves = opt.waves ? opt.waves : 4;
-
-    int rc = MC_OK;
-    auto bail = [&](int code) {
-        if (h->stream) (void)hipStreamSynchronize(h->stream);
-        std::string m = h->err;
-        free_all(h);
-        delete h;
-        g_create_error = m;
-        return code;
-    };
-    if (opt.hip_stream) {
-        h->stream = (hipStream_t)opt.hip_stream;
-    } else {
-        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
-            h->err = "hipStreamCreate failed";
-            return bail(MC_E_DEVICE);
-        }
-        h->own_stream = true;
-    }
-
-    const size_t t4 = h->fp64 ? sizeof(double4) : sizeof(float4);
-    const size_t t1 = h->fp64 ? sizeof(double) : sizeof(float);
-    if ((rc = dalloc(h, &h->pos, 2 * t4 * h->npad)) || (rc = dalloc(h, &h->half, t1 * h->npad)) ||
-        (rc = dalloc(h, &h->charge, t1 * h->npad)) ||
-        (rc = dalloc(h, &h->wall_a, sizeof(double) * h->npad)) ||
-        (rc = dalloc(h, &h->d_type, sizeof(int32_t) * h->npad)) ||
-        (rc = dalloc(h, &h->rec, sizeof(GroupRec) * kRing)) ||
-        (rc = dalloc(h, &h->stats, sizeof(unsigned long long) * ST_N)) ||
-        (rc = dalloc(h, &h->abort_flag, sizeof(int))) ||
-        (rc = dalloc(h, &h->e_partial, sizeof(double) * h->nb)) || (rc = dalloc(h, &h->aux, sizeof(EnergyAux))) ||
-        (rc = dalloc(h, &h->e_state, sizeof(double))) ||
-        (rc = dalloc(h, &h->sweep_tot, sizeof(double) * kMaxLaunchSweeps)) ||
-        (rc = dalloc(h, &h->d_desc, sizeof(ChainDesc))))
-        return bail(rc);
-    const size_t nt = h->species.size();
-    const size_t nh = nt * nt * (size_t)opt.rdf_bins;
-    if ((rc = dalloc(h, &h->rdf_counts, sizeof(unsigned long long) * nh)) ||
-        (rc = dalloc(h, &h->rdf_centres, sizeof(unsigned long long) * nt)))
-        return bail(rc);
-    if (opt.trace_moves > 0) {
-        h->trace_cap = opt.trace_moves;
-        if ((rc = dalloc(h, &h->trace_acc, (size_t)h->trace_cap)) ||
-            (rc = dalloc(h, &h->trace_de, sizeof(double) * h->trace_cap)))
-            return bail(rc);
-    }
-
-    // host images: positions carry the version tag of the sweep that produced
-    // them; the initial state is the result of virtual sweeps -2 (parity 0)
-    // and -1 (parity 1)
-    std::vector<char> hpos(2 * t4 * h->npad), hhalf(t1 * h->npad), hq(t1 * h->npad);
-    std::vector<double> hwall(h->npad, 0.0);
-    for (int i = 0; i < h->npad; ++i) {
-        double x, y, z, qq, hh;
-        if (i < n) {
-            x = positions[3 * i];
-            y = positions[3 * i + 1];
-            z = positions[3 * i + 2];
-            qq = charges[i];
-            hh = 0.5 * diameters[i];
-            hwall[i] = radius - 0.5 * diameters[i];
-        } else {
-            // inert padding ion: no charge, no size, far from everything and from each other
-            x = 1.0e6 * (double)(i - n + 1);
-            y = -2.0e6;
-            z = 3.0e6;
-            qq = 0.0;
-            hh = 0.0;
-        }
-        for (int par = 0; par < 2; ++par) {
-            const uint32_t ver = par == 0 ? 0xFFFFFFFEu : 0xFFFFFFFFu;
-            char* dst = &hpos[t4 * ((size_t)par * h->npad + i)];
-            if (h->fp64) {
-                struct { double x, y, z; uint32_t ver, pad; } r{x, y, z, ver, 0u};
-                std::memcpy(dst, &r, t4);
-            } else {
-                struct { float x, y, z; uint32_t ver; } r{(float)x, (float)y, (float)z, ver};
-                std::memcpy(dst, &r, t4);
-            }
-        }
-        if (h->fp64) {
-            std::memcpy(&hhalf[t1 * i], &hh, t1);
-            std::memcpy(&hq[t1 * i], &qq, t1);
-        } else {
-            float hf = (float)hh, qf = (float)qq;
-            std::memcpy(&hhalf[t1 * i], &hf, t1);
-            std::memcpy(&hq[t1 * i], &qf, t1);
-        }
-    }
-    std::vector<GroupRec> hrec(kRing);
-    for (int k = 0; k < kRing; ++k) {
-        const int64_t g = (int64_t)k - kRing;  // virtual groups -kRing..-1: decided, nothing accepted
-        hrec[(size_t)(g & (kRing - 1))] = GroupRec{(uint32_t)(g + 1), 0u, 0ull};
-    }
-    auto up = [&](void* dst, const void* src, size_t bytes) {
-        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream);
-    };
-    std::vector<unsigned long long> zeros(std::max<size_t>(nh, ST_N), 0ull);
-    int zero = 0;
-    EnergyAux zaux{0.0, 0.0, 0.0, 0ull};
-    hipError_t e = hipSuccess;
-    if ((e = up(h->pos, hpos.data(), 2 * t4 * h->npad)) != hipSuccess ||
-        (e = up(h->half, hhalf.data(), t1 * h->npad)) != hipSuccess ||
-        (e = up(h->charge, hq.data(), t1 * h->npad)) != hipSuccess ||
-        (e = up(h->wall_a, hwall.data(), sizeof(double) * h->npad)) != hipSuccess ||
-        (e = up(h->d_type, h->type.data(), sizeof(int32_t) * h->npad)) != hipSuccess ||
-        (e = up(h->rec, hrec.data(), sizeof(GroupRec) * kRing)) != hipSuccess ||
-        (e = up(h->stats, zeros.data(), sizeof(unsigned long long) * ST_N)) != hipSuccess ||
-        (e = up(h->abort_flag, &zero, sizeof(int))) != hipSuccess ||
-        (e = up(h->aux, &zaux, sizeof(EnergyAux))) != hipSuccess ||
-        (e = up(h->e_state, &zaux.e_resum, sizeof(double))) != hipSuccess ||
-        (e = up(h->rdf_counts, zeros.data(), sizeof(unsigned long long) * nh)) != hipSuccess ||
-        (e = up(h->rdf_centres, zeros.data(), sizeof(unsigned long long) * nt)) != hipSuccess) {
-        h->err = std::string("upload failed: ") + hipGetErrorString(e);
-        return bail(MC_E_DEVICE);
-    }
-    if (h->trace_cap) {
-        if (hipMemsetAsync(h->trace_acc, 0xFF, (size_t)h->trace_cap, h->stream) != hipSuccess) {
-            h->err = "trace init failed";
-            return bail(MC_E_DEVICE);
-        }
-    }
-
-    // launch shape: one workgroup per target group, capped by co-residency
-    SweepFn fn = pick_sweep(h->fp64, h->waves, h->uniform_sigma);
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, 64 * h->waves, 0) != hipSuccess ||
-        per_cu < 1) {
-        h->err = "occupancy query failed for the sweep kernel";
-        return bail(MC_E_DEVICE);
-    }
-    // Every workgroup of the cooperative grid must be resident at once.  The
-    // occupancy query has been seen to over-promise for workgroups with more
-    // than 64 KiB of LDS: such kernels get one workgroup per CU.
-    // Kernels that spill to scratch have been seen to run fewer workgroups at
-    // once than the query reports: they also get one workgroup per CU.
-    hipFuncAttributes fa;
-    if (hipFuncGetAttributes(&fa, (const void*)fn) == hipSuccess &&
-        (fa.sharedSizeBytes > 64 * 1024 || fa.localSizeBytes > 0))
-        per_cu = 1;
-    const int cap = per_cu * h->dev.cus;
-    h->wg = opt.workgroups > 0 ? opt.workgroups : h->nb;
-    h->wg = std::max(1, std::min({h->wg, h->nb, cap}));
-
-    ChainDesc& d = h->desc;
-    d.n = n;
-    d.nb = h->nb;
-    d.band = h->band;
-    d.wg_count = h->wg;
-    d.wg_first = 0;
-    d.chain_id = opt.chain_id;
-    d.seed = 0;
-    d.lB = l_B;
-    d.D = h->D;
-    d.half_uniform = 0.5 * diameters[0];
-    d.pos = h->pos;
-    d.charge = h->charge;
-    d.half = h->half;
-    d.wall_a = h->wall_a;
-    d.rec = h->rec;
-    d.stats = h->stats;
-    d.de_group = nullptr;
-    d.trace_acc = h->trace_acc;
-    d.trace_de = h->trace_de;
-    d.trace_cap = h->trace_cap;
-    std::vector<int32_t> wgmap(h->wg, 0);
-    if ((rc = dalloc(h, &h->d_wgmap, sizeof(int32_t) * h->wg))) return bail(rc);
-    h->wgmap_len = h->wg;
-    if ((e = up(h->d_wgmap, wgmap.data(), sizeof(int32_t) * h->wg)) != hipSuccess ||
-        (e = up(h->d_desc, &d, sizeof(ChainDesc))) != hipSuccess) {
-        h->err = std::string("upload failed: ") + hipGetErrorString(e);
-        return bail(MC_E_DEVICE);
-    }
-    if ((rc = ensure_series(h, 1024))) return bail(rc);
-    // initial energy: re-sum into the running energy
-    if ((rc = launch_energy(h, 1, 0))) return bail(rc);
-    if ((rc = sync_check(h))) return bail(rc);
-    *out = h;
-    return MC_OK;
+int mc_create_batch(int32_t n_chains, const mc_chain_spec* chains, const mc_options* opt_in, mc_handle** out) {
+    if (!out) return fail(nullptr, MC_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_chains < 1 || !chains) return fail(nullptr, MC_E_ARG, "need n_chains >= 1 and a chain array");
+    mc_options opt;
+    mc_options_init(&opt);
+    if (opt_in) opt = *opt_in;
+    int rc = check_options(opt);
+    if (rc) return rc;
+    for (int k = 0; k < n_chains; ++k)
+        if ((rc = validate_chain(chains[k], opt, "chain " + std::to_string(k) + ": "))) return rc;
+    return create_handle(n_chains, chains, opt, out);
 }
 
 int mc_sweep(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
     if (!h) return MC_E_ARG;
     if (h->failed) return fail(h, MC_E_STATE, "handle is in a failed state: " + h->err);
-    if (n_sweeps < 0 || h->sweeps + n_sweeps > (int64_t)UINT32_MAX)
-        return fail(h, MC_E_ARG, "n_sweeps out of range");
-    int64_t left = n_sweeps;
-    while (left > 0) {
-        int64_t step = left;
-        const int re = h->opt.resum_every, rd = h->opt.rdf_every;
-        if (re > 0) step = std::min<int64_t>(step, re - h->sweeps % re);
-        if (rd > 0) step = std::min<int64_t>(step, rd - h->sweeps % rd);
-        int rc = launch_sweeps(h, step, seed);
-        if (rc) return rc;
-        left -= step;
-        if (re > 0 && h->sweeps % re == 0 && (rc = launch_energy(h, 1, 1))) return rc;
-        if (rd > 0 && h->sweeps % rd == 0 && (rc = launch_rdf(h))) return rc;
-    }
-    return MC_OK;
+    return sweep_all(h, n_sweeps, seed);
 }
 
-int mc_energy(mc_handle* h, double* e_running, double* e_exact) {
-    if (!h || !e_running) return h ? fail(h, MC_E_ARG, "null output") : MC_E_ARG;
-    int rc = sync_check(h);
-    if (rc) return rc;
-    HIPCHECK(h, hipMemcpy(e_running, h->e_state, sizeof(double), hipMemcpyDeviceToHost));
-    if (e_exact) {
-        if ((rc = launch_energy(h, 0, 0))) return rc;
-        if ((rc = sync_check(h))) return rc;
-        EnergyAux a;
-        HIPCHECK(h, hipMemcpy(&a, h->aux, sizeof(EnergyAux), hipMemcpyDeviceToHost));
-        *e_exact = a.e_resum;
-    }
-    return MC_OK;
-}
+int mc_energy(mc_handle* h, double* e_running, double* e_exact) { return chain_energy(h, 0, e_running, e_exact); }
 
 int mc_rdf_sample(mc_handle* h) {
     if (!h) return MC_E_ARG;
@@ -694,129 +1039,29 @@ int mc_rdf_reset(mc_handle* h) {
     if (!h) return MC_E_ARG;
     int rc = sync_check(h);
     if (rc) return rc;
-    const size_t nt = h->species.size();
-    HIPCHECK(h, hipMemsetAsync(h->rdf_counts, 0, sizeof(unsigned long long) * nt * nt * h->opt.rdf_bins, h->stream));
-    HIPCHECK(h, hipMemsetAsync(h->rdf_centres, 0, sizeof(unsigned long long) * nt, h->stream));
+    for (Chain& c : h->chains) {
+        const size_t nt = c.species.size();
+        std::vector<unsigned long long> z(nt * nt * (size_t)h->opt.rdf_bins, 0ull);
+        HIPCHECK(h, hipMemcpy(c.rdf_counts, z.data(), sizeof(unsigned long long) * z.size(), hipMemcpyHostToDevice));
+        HIPCHECK(h, hipMemcpy(c.rdf_centres, z.data(), sizeof(unsigned long long) * nt, hipMemcpyHostToDevice));
+    }
     h->rdf_samples = 0;
     return sync_check(h);
 }
 
 int mc_rdf(mc_handle* h, int32_t bins, double* g, uint64_t* counts, uint64_t* centres, int64_t* n_samples) {
-    if (!h) return MC_E_ARG;
-    if (bins != h->opt.rdf_bins) return fail(h, MC_E_ARG, "bins differs from the handle's rdf_bins");
-    int rc = sync_check(h);
-    if (rc) return rc;
-    const size_t nt = h->species.size();
-    const size_t nh = nt * nt * (size_t)bins;
-    std::vector<unsigned long long> c(nh), ce(nt);
-    HIPCHECK(h, hipMemcpy(c.data(), h->rdf_counts, sizeof(unsigned long long) * nh, hipMemcpyDeviceToHost));
-    HIPCHECK(h, hipMemcpy(ce.data(), h->rdf_centres, sizeof(unsigned long long) * nt, hipMemcpyDeviceToHost));
-    if (counts)
-        for (size_t k = 0; k < nh; ++k) counts[k] = c[k];
-    if (centres)
-        for (size_t k = 0; k < nt; ++k) centres[k] = ce[k];
-    if (n_samples) *n_samples = h->rdf_samples;
-    if (g) {
-        const double rmax = h->opt.rdf_rmax, dr = rmax / (double)bins;
-        const double pi = 3.14159265358979323846;
-        for (size_t a = 0; a < nt; ++a)
-            for (size_t b = 0; b < nt; ++b) {
-                const double rb = h->R - 0.5 * h->species[b].second;
-                const double vb = 4.0 / 3.0 * pi * rb * rb * rb;
-                const double nbd = (double)(h->n_of_type[b] - (a == b ? 1 : 0)) / vb;
-                for (int k = 0; k < bins; ++k) {
-                    const double r0 = k * dr, r1 = (k + 1) * dr;
-                    const double vk = 4.0 / 3.0 * pi * (r1 * r1 * r1 - r0 * r0 * r0);
-                    const double den = (double)ce[a] * nbd * vk;
-                    g[(a * nt + b) * bins + k] = den > 0 ? (double)c[(a * nt + b) * bins + k] / den : 0.0;
-                }
-            }
-    }
-    return MC_OK;
+    return chain_rdf(h, 0, bins, g, counts, centres, n_samples);
 }
 
-int mc_species(const mc_handle* h, int32_t* ntypes, double* q, double* s) {
-    if (!h) return MC_E_ARG;
-    if (ntypes) *ntypes = (int32_t)h->species.size();
-    for (size_t k = 0; k < h->species.size(); ++k) {
-        if (q) q[k] = h->species[k].first;
-        if (s) s[k] = h->species[k].second;
-    }
-    return MC_OK;
-}
+int mc_species(const mc_handle* h, int32_t* ntypes, double* q, double* s) { return chain_species(h, 0, ntypes, q, s); }
 
-int mc_get_positions(mc_handle* h, double* xyz) {
-    if (!h || !xyz) return h ? fail(h, MC_E_ARG, "null output") : MC_E_ARG;
-    int rc = sync_check(h);
-    if (rc) return rc;
-    const int parity = (int)((h->sweeps - 1) & 1);
-    if (h->fp64) {
-        std::vector<double4> v(h->n);
-        HIPCHECK(h, hipMemcpy(v.data(), (double4*)h->pos + (size_t)parity * h->npad, sizeof(double4) * h->n,
-                              hipMemcpyDeviceToHost));
-        for (int i = 0; i < h->n; ++i) {
-            xyz[3 * i] = v[i].x;
-            xyz[3 * i + 1] = v[i].y;
-            xyz[3 * i + 2] = v[i].z;
-        }
-    } else {
-        std::vector<float4> v(h->n);
-        HIPCHECK(h, hipMemcpy(v.data(), (float4*)h->pos + (size_t)parity * h->npad, sizeof(float4) * h->n,
-                              hipMemcpyDeviceToHost));
-        for (int i = 0; i < h->n; ++i) {
-            xyz[3 * i] = v[i].x;
-            xyz[3 * i + 1] = v[i].y;
-            xyz[3 * i + 2] = v[i].z;
-        }
-    }
-    return MC_OK;
-}
+int mc_get_positions(mc_handle* h, double* xyz) { return chain_positions(h, 0, xyz); }
 
-int mc_trace(mc_handle* h, int64_t n_moves, uint8_t* acc, double* dE) {
-    if (!h) return MC_E_ARG;
-    if (n_moves < 0 || n_moves > h->trace_cap || n_moves > h->sweeps * (int64_t)h->n)
-        return fail(h, MC_E_ARG, "n_moves exceeds the traced moves");
-    int rc = sync_check(h);
-    if (rc) return rc;
-    if (acc && n_moves) HIPCHECK(h, hipMemcpy(acc, h->trace_acc, (size_t)n_moves, hipMemcpyDeviceToHost));
-    if (dE && n_moves) HIPCHECK(h, hipMemcpy(dE, h->trace_de, sizeof(double) * n_moves, hipMemcpyDeviceToHost));
-    return MC_OK;
-}
+int mc_trace(mc_handle* h, int64_t n_moves, uint8_t* acc, double* dE) { return chain_trace(h, 0, n_moves, acc, dE); }
 
-int mc_energy_series(mc_handle* h, int64_t n, double* e) {
-    if (!h) return MC_E_ARG;
-    if (n < 0 || n > h->sweeps || (n && !e)) return fail(h, MC_E_ARG, "n exceeds the sweeps done");
-    int rc = sync_check(h);
-    if (rc) return rc;
-    if (n) HIPCHECK(h, hipMemcpy(e, h->e_series, sizeof(double) * n, hipMemcpyDeviceToHost));
-    return MC_OK;
-}
+int mc_energy_series(mc_handle* h, int64_t n, double* e) { return chain_energy_series(h, 0, n, e); }
 
-int mc_get_stats(mc_handle* h, mc_stats* out) {
-    if (!h || !out) return h ? fail(h, MC_E_ARG, "null output") : MC_E_ARG;
-    int rc = sync_check(h);
-    if (rc) return rc;
-    unsigned long long st[ST_N];
-    EnergyAux a;
-    HIPCHECK(h, hipMemcpy(st, h->stats, sizeof(st), hipMemcpyDeviceToHost));
-    HIPCHECK(h, hipMemcpy(&a, h->aux, sizeof(a), hipMemcpyDeviceToHost));
-    std::memset(out, 0, sizeof(*out));
-    out->sweeps = h->sweeps;
-    out->moves = (int64_t)st[ST_MOVES];
-    out->accepted = (int64_t)st[ST_ACC];
-    out->rejected_wall = (int64_t)st[ST_WALL];
-    out->rejected_overlap = (int64_t)st[ST_OVERLAP];
-    out->rejected_metropolis = (int64_t)st[ST_METRO];
-    out->fixpoint_iterations = (int64_t)st[ST_ITERS];
-    out->early_groups = (int64_t)st[ST_EARLY];
-    out->resums = (int64_t)a.n_resum;
-    out->last_drift = a.drift_last;
-    out->max_abs_drift = a.drift_max;
-    out->band = h->band;
-    out->waves = h->waves;
-    out->workgroups = h->wg;
-    return MC_OK;
-}
+int mc_get_stats(mc_handle* h, mc_stats* out) { return chain_stats(h, 0, out); }
 
 int mc_timing(mc_handle* h, int64_t* launches, double* kernel_ms, int64_t* sweeps) {
     if (!h) return MC_E_ARG;
@@ -849,9 +1094,147 @@ int mc_timing_reset(mc_handle* h) {
 int mc_set_max_disp(mc_handle* h, double max_disp) {
     if (!h) return MC_E_ARG;
     if (!is_finite(max_disp) || max_disp <= 0) return fail(h, MC_E_ARG, "max_disp must be > 0");
-    h->D = 2.0 * max_disp;
-    h->desc.D = h->D;
+    for (Chain& c : h->chains) c.D = 2.0 * max_disp;
     return upload_desc(h);
+}
+
+int mc_chain_count(const mc_handle* h, int32_t* n_chains) {
+    if (!h || !n_chains) return MC_E_ARG;
+    *n_chains = (int32_t)h->chains.size();
+    return MC_OK;
+}
+
+int mc_chain_energy(mc_handle* h, int32_t chain, double* e_running, double* e_exact) {
+    return chain_energy(h, chain, e_running, e_exact);
+}
+
+int mc_chain_rdf(mc_handle* h, int32_t chain, int32_t bins, double* g, uint64_t* counts, uint64_t* centres,
+                 int64_t* n_samples) {
+    return chain_rdf(h, chain, bins, g, counts, centres, n_samples);
+}
+
+int mc_chain_species(const mc_handle* h, int32_t chain, int32_t* ntypes, double* charges, double* diameters) {
+    return chain_species(h, chain, ntypes, charges, diameters);
+}
+
+int mc_chain_positions(mc_handle* h, int32_t chain, double* xyz) { return chain_positions(h, chain, xyz); }
+
+int mc_chain_trace(mc_handle* h, int32_t chain, int64_t n_moves, uint8_t* acc, double* dE) {
+    return chain_trace(h, chain, n_moves, acc, dE);
+}
+
+int mc_chain_energy_series(mc_handle* h, int32_t chain, int64_t n, double* e) {
+    return chain_energy_series(h, chain, n, e);
+}
+
+int mc_chain_stats(mc_handle* h, int32_t chain, mc_stats* out) { return chain_stats(h, chain, out); }
+
+int mc_chain_set_max_disp(mc_handle* h, int32_t chain, double max_disp) {
+    return chain_set_max_disp(h, chain, max_disp);
+}
+
+int mc_get_schedule(const mc_handle* h, int32_t* workgroups, double* model) {
+    if (!h) return MC_E_ARG;
+    if (workgroups)
+        for (size_t k = 0; k < h->chains.size(); ++k) workgroups[k] = h->chains[k].wg;
+    if (model) {
+        model[0] = h->model_a;
+        model[1] = h->model_b;
+    }
+    return MC_OK;
+}
+
+int mc_set_schedule(mc_handle* h, const int32_t* workgroups) {
+    if (!h || !workgroups) return h ? fail(h, MC_E_ARG, "null workgroups") : MC_E_ARG;
+    int total = 0;
+    for (size_t k = 0; k < h->chains.size(); ++k) {
+        if (workgroups[k] < 1 || workgroups[k] > h->chains[k].nb)
+            return fail(h, MC_E_ARG, "chain " + std::to_string(k) + ": workgroups must be in [1, groups of 64]");
+        total += workgroups[k];
+    }
+    if (total > h->cap)
+        return fail(h, MC_E_ARG, "total workgroups exceed the co-resident capacity " + std::to_string(h->cap));
+    int rc = sync_check(h);
+    if (rc) return rc;
+    std::vector<int> wg(workgroups, workgroups + h->chains.size());
+    std::vector<std::pair<double, int2>> per;
+    for (size_t k = 0; k < h->chains.size(); ++k)
+        for (int j = 0; j < wg[k]; ++j)
+            per.emplace_back((double)h->chains[k].nb * h->chains[k].nb / wg[k], make_int2((int)k, j));
+    std::stable_sort(per.begin(), per.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    const int W = (int)per.size(), half = (W + 1) / 2;
+    std::vector<int2> map(W);
+    for (int q = 0; q < W; ++q) map[q < half ? q : W - 1 - (q - half)] = per[q].second;
+    return apply_schedule(h, wg, map);
+}
+
+int mc_chain_launch_ms(mc_handle* h, double* ms) {
+    if (!h || !ms) return h ? fail(h, MC_E_ARG, "null output") : MC_E_ARG;
+    std::vector<double> v;
+    int rc = last_launch_ms(h, v);
+    if (rc) return rc;
+    for (size_t k = 0; k < v.size(); ++k) ms[k] = v[k];
+    return MC_OK;
+}
+
+int mc_autotune(mc_handle* h, int32_t calib_sweeps, uint64_t seed, double* model) {
+    if (!h) return MC_E_ARG;
+    if (calib_sweeps < 1 || calib_sweeps > kMaxLaunchSweeps)
+        return fail(h, MC_E_ARG, "calib_sweeps must be in [1, 4096]");
+    if (h->failed) return fail(h, MC_E_STATE, "handle is in a failed state: " + h->err);
+    // one calibration launch (real sweeps of every chain) on the current schedule
+    int rc = launch_sweeps(h, calib_sweeps, seed);
+    if (rc) return rc;
+    std::vector<double> ms;
+    if ((rc = last_launch_ms(h, ms))) return rc;
+    // least squares, relative error: t_c / S = a nb_c + b nb_c^2 / w_c (microseconds)
+    double s11 = 0, s12 = 0, s22 = 0, r1 = 0, r2 = 0;
+    int used = 0;
+    for (size_t k = 0; k < h->chains.size(); ++k) {
+        const Chain& c = h->chains[k];
+        const double t = 1e3 * ms[k] / calib_sweeps;
+        if (!(t > 0)) continue;
+        const double x1 = c.nb / t, x2 = (double)c.nb * c.nb / c.wg / t;  // weight 1/t
+        s11 += x1 * x1;
+        s12 += x1 * x2;
+        s22 += x2 * x2;
+        r1 += x1;
+        r2 += x2;
+        ++used;
+    }
+    double a = h->model_a, b = h->model_b;
+    const double det = s11 * s22 - s12 * s12;
+    if (used >= 2 && det > 1e-12 * s11 * s22) {
+        a = (r1 * s22 - r2 * s12) / det;
+        b = (s11 * r2 - s12 * r1) / det;
+    }
+    if (!(a > 0) || !(b > 0)) {
+        // degenerate fit (e.g. one chain): one-parameter fits, keeping the model's ratio
+        double num = 0, den = 0;
+        for (size_t k = 0; k < h->chains.size(); ++k) {
+            const Chain& c = h->chains[k];
+            const double t = 1e3 * ms[k] / calib_sweeps;
+            if (!(t > 0)) continue;
+            const double f = (h->model_a * c.nb + h->model_b * (double)c.nb * c.nb / c.wg) / t;
+            num += f;
+            den += f * f;
+        }
+        const double scale = den > 0 ? num / den : 1.0;
+        a = h->model_a * scale;
+        b = h->model_b * scale;
+    }
+    h->model_a = a;
+    h->model_b = b;
+    if (model) {
+        model[0] = a;
+        model[1] = b;
+    }
+    std::vector<int> wg;
+    std::vector<int2> map;
+    plan_schedule(h, wg, map);
+    if ((rc = apply_schedule(h, wg, map))) return rc;
+    if (h->opt.resum_every > 0 && h->sweeps % h->opt.resum_every == 0 && (rc = launch_energy(h, 1, 1))) return rc;
+    return MC_OK;
 }
 
 void mc_destroy(mc_handle* h) {

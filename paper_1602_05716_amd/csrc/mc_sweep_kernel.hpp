@@ -51,7 +51,7 @@ struct ChainDesc {
     int32_t nb;          // groups of 64 (last one padded with inert ions)
     int32_t band;        // look-ahead band in groups, 0..min(kMaxBand, nb-1)
     int32_t wg_count;    // workgroups serving this chain
-    int32_t wg_first;    // first workgroup index of this chain in the grid
+    int32_t npad;        // nb * 64
     uint32_t chain_id;   // Philox counter word 2
     uint64_t seed;       // Philox key
     double lB;           // Bjerrum length
@@ -67,6 +67,21 @@ struct ChainDesc {
     uint8_t* trace_acc;  // [trace_cap]
     double* trace_de;    // [trace_cap]
     int64_t trace_cap;   // moves traced from the start of the chain
+    unsigned long long* clk;  // [2] wall clock at the launch start and when the
+                              // chain's last group of the launch was published
+    // energy bookkeeping and g(r) (auxiliary kernels)
+    double* e_partial;   // [(nb + 1) / 2] re-sum partials
+    void* aux;           // EnergyAux
+    double* e_state;     // running energy
+    double* sweep_tot;   // [max sweeps per launch] scratch of the scan
+    double* e_series;    // [e_capacity] running energy after each sweep
+    int64_t e_capacity;
+    const int32_t* type; // [npad] species index, -1 for padding
+    int32_t ntypes;
+    int32_t pad0;
+    double rdf_rc;       // centres need |x| <= rdf_rc
+    unsigned long long* rdf_counts;   // [ntypes * ntypes * bins]
+    unsigned long long* rdf_centres;  // [ntypes]
 };
 
 // A position record is {x, y, z, version}: version = sweep index (mod 2^32)
@@ -449,7 +464,7 @@ constexpr int kWavesPerEU = sizeof(T) == 4 ? (M == 8 ? 4 : 2) : 1;
 template <typename T, int M, bool UNIFORM_SIGMA>
 __global__ void __launch_bounds__(64 * M)
 __attribute__((amdgpu_waves_per_eu(kWavesPerEU<T, M>)))
-sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ wg_chain,
+sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_map,
              uint32_t s0, int32_t n_sweeps, Ctl ctl)
 {
     using T4 = typename Prec<T>::T4;
@@ -460,8 +475,10 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const ChainDesc& cd = chains[wg_chain[blockIdx.x]];
-    const int k_wg = (int)blockIdx.x - cd.wg_first;
+    // workgroup -> (chain, index of the workgroup among the chain's)
+    const int2 wm = wg_map[blockIdx.x];
+    const ChainDesc& cd = chains[wm.x];
+    const int k_wg = wm.y;
 
     const int nb = cd.nb, band = cd.band;
     const int npad = nb * kGroup;
@@ -477,6 +494,7 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
     if (threadIdx.x == 0) {
         sh.ready = 0;
         sh.consumed = 0;
+        if (k_wg == 0) cd.clk[0] = wall_clock64();
     }
     __syncthreads();
 
@@ -695,9 +713,11 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
                 __hip_atomic_fetch_add(&sh.ready, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 
             // ---- wave 0 finishes the group: decisions and publication
-            if (wave == 0)
+            if (wave == 0) {
                 chain_step<T, M>(sh, cd, pos_r, rec_r, charge, g_begin, g, t, xi, yi, zi, txi, tyi, tzi,
                                  wd.w, ctl, c_moves, c_acc, c_wall, c_ov, c_iters, c_early);
+                if (g == g_end - 1 && lane == 0) cd.clk[1] = wall_clock64();
+            }
         }
     }
     if (wave == 0 && lane == 0 && c_moves) {
@@ -711,27 +731,27 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int32_t* __restrict__ w
     }
 }
 
-// Running energy after each sweep of a launch: per-sweep totals of the group
-// energy changes (each summed in group order), then a serial prefix from the
-// previous running energy.  Deterministic.
+// Running energy after each sweep of a launch, one block per chain:
+// per-sweep totals of the group energy changes (each summed in group order),
+// then a serial prefix from the previous running energy.  Deterministic.
 __global__ void __launch_bounds__(256)
-energy_scan_kernel(const double* __restrict__ de_group, int nb, int32_t n_sweeps, int64_t s0,
-                   double* __restrict__ sweep_tot, double* __restrict__ e_state,
-                   double* __restrict__ e_series, int64_t e_capacity)
+energy_scan_kernel(const ChainDesc* __restrict__ chains, int32_t n_sweeps, int64_t s0)
 {
+    const ChainDesc& cd = chains[blockIdx.x];
+    const int nb = cd.nb;
     for (int s = threadIdx.x; s < n_sweeps; s += blockDim.x) {
         double t = 0.0;
-        for (int b = 0; b < nb; ++b) t += de_group[(int64_t)s * nb + b];
-        sweep_tot[s] = t;
+        for (int b = 0; b < nb; ++b) t += cd.de_group[(int64_t)s * nb + b];
+        cd.sweep_tot[s] = t;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double e = *e_state;
+        double e = *cd.e_state;
         for (int s = 0; s < n_sweeps; ++s) {
-            e += sweep_tot[s];
-            if (s0 + s < e_capacity) e_series[s0 + s] = e;
+            e += cd.sweep_tot[s];
+            if (s0 + s < cd.e_capacity) cd.e_series[s0 + s] = e;
         }
-        *e_state = e;
+        *cd.e_state = e;
     }
 }
 

@@ -55,11 +55,23 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class ChainSpec(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("charges", ctypes.POINTER(ctypes.c_double)),
+                ("diameters", ctypes.POINTER(ctypes.c_double)),
+                ("positions", ctypes.POINTER(ctypes.c_double)),
+                ("radius", ctypes.c_double), ("l_B", ctypes.c_double), ("max_disp", ctypes.c_double),
+                ("chain_id", ctypes.c_uint32), ("reserved1", ctypes.c_int32)]
+
+
 # Every symbol include/mc.h declares.
 SYMBOLS = ["mc_options_init", "mc_create", "mc_sweep", "mc_energy", "mc_rdf", "mc_rdf_sample",
            "mc_rdf_reset", "mc_species", "mc_get_positions", "mc_trace", "mc_energy_series",
-           "mc_get_stats", "mc_timing", "mc_timing_reset", "mc_set_max_disp", "mc_destroy",
-           "mc_last_error"]
+           "mc_get_stats", "mc_timing", "mc_timing_reset", "mc_set_max_disp",
+           "mc_create_batch", "mc_chain_count", "mc_chain_energy", "mc_chain_rdf", "mc_chain_species",
+           "mc_chain_positions", "mc_chain_trace", "mc_chain_energy_series", "mc_chain_stats",
+           "mc_chain_set_max_disp", "mc_get_schedule", "mc_set_schedule", "mc_chain_launch_ms",
+           "mc_autotune", "mc_destroy", "mc_last_error"]
 
 _f64p = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -90,6 +102,21 @@ def load(path: str = LIB_PATH):
         "mc_timing": ([_hp, _i64p, _f64p, _i64p], ctypes.c_int),
         "mc_timing_reset": ([_hp], ctypes.c_int),
         "mc_set_max_disp": ([_hp, ctypes.c_double], ctypes.c_int),
+        "mc_create_batch": ([ctypes.c_int32, ctypes.POINTER(ChainSpec), ctypes.POINTER(Options),
+                             ctypes.POINTER(_hp)], ctypes.c_int),
+        "mc_chain_count": ([_hp, _i32p], ctypes.c_int),
+        "mc_chain_energy": ([_hp, ctypes.c_int32, _f64p, _f64p], ctypes.c_int),
+        "mc_chain_rdf": ([_hp, ctypes.c_int32, ctypes.c_int32, _f64p, _u64p, _u64p, _i64p], ctypes.c_int),
+        "mc_chain_species": ([_hp, ctypes.c_int32, _i32p, _f64p, _f64p], ctypes.c_int),
+        "mc_chain_positions": ([_hp, ctypes.c_int32, _f64p], ctypes.c_int),
+        "mc_chain_trace": ([_hp, ctypes.c_int32, ctypes.c_int64, _u8p, _f64p], ctypes.c_int),
+        "mc_chain_energy_series": ([_hp, ctypes.c_int32, ctypes.c_int64, _f64p], ctypes.c_int),
+        "mc_chain_stats": ([_hp, ctypes.c_int32, ctypes.POINTER(Stats)], ctypes.c_int),
+        "mc_chain_set_max_disp": ([_hp, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
+        "mc_get_schedule": ([_hp, _i32p, _f64p], ctypes.c_int),
+        "mc_set_schedule": ([_hp, _i32p], ctypes.c_int),
+        "mc_chain_launch_ms": ([_hp, _f64p], ctypes.c_int),
+        "mc_autotune": ([_hp, ctypes.c_int32, ctypes.c_uint64, _f64p], ctypes.c_int),
         "mc_destroy": ([_hp], None),
         "mc_last_error": ([_hp], ctypes.c_char_p),
     }
@@ -215,6 +242,158 @@ class Chain:
 
     def set_max_disp(self, v):
         self._check(self._L.mc_set_max_disp(self.h, float(v)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.mc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Batch:
+    """Independent chains served by one persistent launch (mc_create_batch).
+
+    ``systems`` is a sequence of (xyz, q, sigma, R, lB) or of objects with
+    those attributes (``inputs.System``); ``max_disp`` and ``chain_ids`` are
+    optional per-chain sequences.  Methods taking ``c`` address one chain.
+    """
+
+    def __init__(self, systems, max_disp=None, chain_ids=None, **opts):
+        self._L = lib()
+        self.opt = options(**opts)
+        self._keep = []
+        specs = (ChainSpec * len(systems))()
+        self.n = []
+        for k, sy in enumerate(systems):
+            if isinstance(sy, tuple):
+                xyz, q, sigma, R, lB = sy
+            else:
+                xyz, q, sigma, R, lB = sy.xyz, sy.q, sy.sigma, sy.R, sy.lB
+            q = np.ascontiguousarray(q, np.float64)
+            sg = np.ascontiguousarray(sigma, np.float64)
+            x = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)
+            self._keep += [q, sg, x]
+            specs[k].n = len(q)
+            specs[k].charges = _p(q, _f64p)
+            specs[k].diameters = _p(sg, _f64p)
+            specs[k].positions = _p(x, _f64p)
+            specs[k].radius = float(R)
+            specs[k].l_B = float(lB)
+            specs[k].max_disp = 0.0 if max_disp is None else float(max_disp[k])
+            specs[k].chain_id = k if chain_ids is None else int(chain_ids[k])
+            self.n.append(len(q))
+        h = _hp()
+        rc = self._L.mc_create_batch(len(systems), specs, ctypes.byref(self.opt), ctypes.byref(h))
+        self._keep = []
+        if rc != MC_OK:
+            raise MCError(rc, self._L.mc_last_error(None).decode())
+        self.h = h
+        self.count = len(systems)
+
+    def _check(self, rc):
+        if rc != MC_OK:
+            raise MCError(rc, self._L.mc_last_error(self.h).decode())
+
+    def sweep(self, n_sweeps, seed):
+        self._check(self._L.mc_sweep(self.h, int(n_sweeps), int(seed)))
+
+    def energy(self, c, exact=False):
+        er = ctypes.c_double()
+        ee = ctypes.c_double()
+        self._check(self._L.mc_chain_energy(self.h, int(c), ctypes.byref(er), ctypes.byref(ee) if exact else None))
+        return (er.value, ee.value) if exact else er.value
+
+    def positions(self, c):
+        out = np.zeros((self.n[c], 3), np.float64)
+        self._check(self._L.mc_chain_positions(self.h, int(c), _p(out, _f64p)))
+        return out
+
+    def trace(self, c, n_moves):
+        acc = np.zeros(n_moves, np.uint8)
+        de = np.zeros(n_moves, np.float64)
+        self._check(self._L.mc_chain_trace(self.h, int(c), int(n_moves), _p(acc, _u8p), _p(de, _f64p)))
+        return acc, de
+
+    def energy_series(self, c, n):
+        e = np.zeros(n, np.float64)
+        self._check(self._L.mc_chain_energy_series(self.h, int(c), int(n), _p(e, _f64p)))
+        return e
+
+    def species(self, c):
+        nt = ctypes.c_int32()
+        self._check(self._L.mc_chain_species(self.h, int(c), ctypes.byref(nt), None, None))
+        q = np.zeros(nt.value)
+        s = np.zeros(nt.value)
+        self._check(self._L.mc_chain_species(self.h, int(c), None, _p(q, _f64p), _p(s, _f64p)))
+        return q, s
+
+    def rdf_sample(self):
+        self._check(self._L.mc_rdf_sample(self.h))
+
+    def rdf_reset(self):
+        self._check(self._L.mc_rdf_reset(self.h))
+
+    def rdf(self, c):
+        q, _ = self.species(c)
+        nt = len(q)
+        bins = self.opt.rdf_bins
+        g = np.zeros((nt, nt, bins))
+        cnt = np.zeros((nt, nt, bins), np.uint64)
+        ce = np.zeros(nt, np.uint64)
+        ns = ctypes.c_int64()
+        self._check(self._L.mc_chain_rdf(self.h, int(c), bins, _p(g, _f64p), _p(cnt, _u64p), _p(ce, _u64p),
+                                         ctypes.byref(ns)))
+        return {"g": g, "counts": cnt, "centres": ce, "samples": ns.value}
+
+    def stats(self, c):
+        st = Stats()
+        self._check(self._L.mc_chain_stats(self.h, int(c), ctypes.byref(st)))
+        return st.as_dict()
+
+    def set_max_disp(self, c, v):
+        self._check(self._L.mc_chain_set_max_disp(self.h, int(c), float(v)))
+
+    def schedule(self):
+        """(workgroups per chain, cost model (a, b) in microseconds)."""
+        w = np.zeros(self.count, np.int32)
+        m = np.zeros(2, np.float64)
+        self._check(self._L.mc_get_schedule(self.h, _p(w, _i32p), _p(m, _f64p)))
+        return w, (float(m[0]), float(m[1]))
+
+    def set_schedule(self, workgroups):
+        w = np.ascontiguousarray(workgroups, np.int32)
+        self._check(self._L.mc_set_schedule(self.h, _p(w, _i32p)))
+
+    def launch_ms(self):
+        ms = np.zeros(self.count, np.float64)
+        self._check(self._L.mc_chain_launch_ms(self.h, _p(ms, _f64p)))
+        return ms
+
+    def autotune(self, calib_sweeps, seed):
+        m = np.zeros(2, np.float64)
+        self._check(self._L.mc_autotune(self.h, int(calib_sweeps), int(seed), _p(m, _f64p)))
+        return float(m[0]), float(m[1])
+
+    def timing(self):
+        la = ctypes.c_int64()
+        ms = ctypes.c_double()
+        sw = ctypes.c_int64()
+        self._check(self._L.mc_timing(self.h, ctypes.byref(la), ctypes.byref(ms), ctypes.byref(sw)))
+        return la.value, ms.value, sw.value
+
+    def timing_reset(self):
+        self._check(self._L.mc_timing_reset(self.h))
 
     def close(self):
         if getattr(self, "h", None):

@@ -94,3 +94,65 @@ def test_binding_fails_loudly_without_library(tmp_path):
     from paper_1602_05716_amd import mc
     with pytest.raises(mc.MCLibraryError):
         mc.load(str(tmp_path / "missing.so"))
+
+
+def _create_batch(specs, **kw):
+    """specs: list of (q, sigma, xyz, R, lB); returns (rc, message)."""
+    from paper_1602_05716_amd import mc
+    L = mc.lib()
+    arr = (mc.ChainSpec * len(specs))()
+    keep = []
+    for k, (q, s, x, R, lB) in enumerate(specs):
+        q = np.ascontiguousarray(q, np.float64)
+        s = np.ascontiguousarray(s, np.float64)
+        x = np.ascontiguousarray(x, np.float64)
+        keep += [q, s, x]
+        arr[k].n = len(q)
+        arr[k].charges = q.ctypes.data_as(mc._f64p)
+        arr[k].diameters = s.ctypes.data_as(mc._f64p)
+        arr[k].positions = x.ctypes.data_as(mc._f64p)
+        arr[k].radius = R
+        arr[k].l_B = lB
+        arr[k].chain_id = k
+    h = ctypes.c_void_p()
+    o = mc.options(**kw)
+    rc = L.mc_create_batch(len(specs), arr, ctypes.byref(o), ctypes.byref(h))
+    msg = L.mc_last_error(None).decode()
+    if rc == 0:
+        L.mc_destroy(h)
+    assert not (rc != 0 and h.value), "handle leaked on error"
+    return rc, msg
+
+
+def test_create_batch_validates_every_chain():
+    good = ([1.0, -1.0], [1.0, 1.0], [[0, 0, 0], [3, 0, 0]], 10.0, 0.7)
+    bad_neutral = ([1.0, 1.0], [1.0, 1.0], [[0, 0, 0], [3, 0, 0]], 10.0, 0.7)
+    bad_wall = ([1.0, -1.0], [1.0, 1.0], [[0, 0, 0], [9.6, 0, 0]], 10.0, 0.7)
+    bad_overlap = ([1.0, -1.0], [1.0, 1.0], [[0, 0, 0], [0.9, 0, 0]], 10.0, 0.7)
+    rc, msg = _create_batch([good, bad_neutral])
+    assert rc == -4 and msg.startswith("chain 1:"), msg
+    rc, msg = _create_batch([bad_wall, good])
+    assert rc == -3 and msg.startswith("chain 0:"), msg
+    rc, msg = _create_batch([good, good, bad_overlap])
+    assert rc == -2 and msg.startswith("chain 2:"), msg
+    rc, msg = _create_batch([good], max_disp=-1.0)
+    assert rc == -1, msg
+
+
+def test_create_batch_rejects_empty_and_null():
+    from paper_1602_05716_amd import mc
+    L = mc.lib()
+    h = ctypes.c_void_p()
+    assert L.mc_create_batch(0, None, None, ctypes.byref(h)) == -1 and not h.value
+    assert L.mc_create_batch(1, None, None, ctypes.byref(h)) == -1 and not h.value
+
+
+def test_chain_calls_reject_null_handle():
+    from paper_1602_05716_amd import mc
+    L = mc.lib()
+    n = ctypes.c_int32()
+    assert L.mc_chain_count(None, ctypes.byref(n)) == -1
+    assert L.mc_get_schedule(None, None, None) == -1
+    assert L.mc_set_schedule(None, None) == -1
+    assert L.mc_autotune(None, 1, 0, None) == -1
+    assert L.mc_chain_launch_ms(None, None) == -1
