@@ -118,6 +118,75 @@ def run_valu_probe():
         return None
 
 
+def batched_leg(args, log_fn=None):
+    """Batched ensemble: 256 independent 1:1 chains (N log-uniform in [500,
+    8000], phi uniform in [0.005, 0.1], l_B uniform in [0.5, 2]) in one
+    persistent launch with the autotuned schedule, against the same chains
+    run one after another with the single-chain path.
+
+    A chain's trajectory does not depend on the schedule (tested), so both
+    modes give every chain the same energy series and the same ESS; only the
+    wall time differs.  The one-after-another time of each chain is measured
+    alone on ``seq_sweeps`` sweeps of the same stretch and scaled to the
+    batched sweep count."""
+    import torch
+    from paper_1602_05716_amd import analysis, inputs, mc
+    params = inputs.ensemble_params(256)
+    systems = [inputs.ensemble_chain(*p) for p in params]
+    nsum = sum(s.n for s in systems)
+    pairs = sum(s.n * (s.n - 1) for s in systems)
+    S, seed = args.batch_sweeps, 0x5EED0004
+    stream = torch.cuda.Stream()
+    b = mc.Batch(systems, precision="fp32", max_disp=[0.5] * len(systems), resum_every=100,
+                 hip_stream=stream.cuda_stream, record_timing=1)
+    # warm-up: per-chain move-size tuning, then the autotuner, then equilibration
+    md = np.full(len(systems), 0.5)
+    for r in range(8):
+        st0 = [b.stats(k) for k in range(len(systems))]
+        b.sweep(4, 0xD15C + r)
+        for k in range(len(systems)):
+            st1 = b.stats(k)
+            acc = (st1["accepted"] - st0[k]["accepted"]) / max(1, st1["moves"] - st0[k]["moves"])
+            md[k] *= min(2.0, max(0.5, acc / 0.40))
+            b.set_max_disp(k, md[k])
+    model = b.autotune(2, seed)
+    b.sweep(66, seed)  # equilibration up to a multiple of the re-sum interval
+    s0 = b.stats(0)["sweeps"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.sweep(S, seed)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    ess = []
+    for k in range(len(systems)):
+        e = b.energy_series(k, s0 + S)[s0:]
+        ess.append(analysis.effective_samples(e))
+    w, _ = b.schedule()
+    b.close()
+    # the same chains, one at a time, same state and parameters at the start of the timed stretch
+    t_seq = 0.0
+    for k, sy in enumerate(systems):
+        ch = mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision="fp32", max_disp=float(md[k]),
+                      chain_id=k, resum_every=100, hip_stream=stream.cuda_stream)
+        ch.sweep(2, 0)  # the cost of a sweep does not depend on which sweep it is
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ch.sweep(args.seq_sweeps, seed)
+        torch.cuda.synchronize()
+        t_seq += (time.perf_counter() - t1) * S / args.seq_sweeps
+        ch.close()
+    ess_tot = float(np.nansum(ess))
+    return {"workload": "256 independent 1:1 chains, N log-uniform [500, 8000] (sum %d), phi U[0.005, 0.1], "
+                        "l_B U[0.5, 2], move size tuned per chain to ~40%% acceptance" % nsum,
+            "chains": len(systems), "sum_n": nsum, "sweeps": S,
+            "wall_s": t_batch, "moves_per_s": S * nsum / t_batch, "pair_terms_per_s": S * pairs / t_batch,
+            "ess_total": ess_tot, "ess_per_s": ess_tot / t_batch,
+            "workgroups_total": int(w.sum()), "cost_model_us": {"a": model[0], "b": model[1]},
+            "one_after_another": {"wall_s": t_seq, "ess_per_s": ess_tot / t_seq,
+                                  "measured_sweeps_per_chain": args.seq_sweeps},
+            "batched_over_sequential": t_seq / t_batch}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +199,9 @@ def main():
     ap.add_argument("--no-probe", action="store_true", help="skip the VALU issue-rate probe")
     ap.add_argument("--band", type=int, default=-1)
     ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--batch-sweeps", type=int, default=1000)
+    ap.add_argument("--seq-sweeps", type=int, default=20)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -195,6 +267,11 @@ def main():
     if probe:
         roofline["probe"] = probe
 
+    batched = None
+    if not args.no_batched:
+        log("batched ensemble leg")
+        batched = batched_leg(args)
+
     cpu = None
     if not args.no_cpu:
         log("timing the CPU oracle (%d sweep(s))" % args.cpu_sweeps)
@@ -214,7 +291,11 @@ def main():
                    "max_disp": md, "acceptance": acc, "band": st1["band"], "waves": st1["waves"],
                    "workgroups": st1["workgroups"]},
         "pair_terms_per_s": pairs / elapsed,
-        "ess_per_s": {"plain": ess / elapsed, "batched": None, "surrogate_da": None},
+        "ess_per_s": {"plain": ess / elapsed,
+                      "batched": batched["ess_per_s"] if batched else None,
+                      "batched_one_after_another": batched["one_after_another"]["ess_per_s"] if batched else None,
+                      "surrogate_da": None},
+        "batched": batched,
         "energy": {"tau_int_sweeps": tau, "e_running": e_run, "e_resum": e_exact,
                    "max_abs_drift_per_resum": st1["max_abs_drift"]},
         "roofline": roofline,
