@@ -315,3 +315,225 @@ void orc_rdf_counts(int32_t n, const double* xyz, const int32_t* type, int32_t n
         }
     }
 }
+
+/* ======================================================================== */
+/* Delayed acceptance with a learned first stage (not in the paper).          */
+/*                                                                            */
+/* Two-stage Metropolis (Christen and Fox, J. Comput. Graph. Stat. 14, 2005): */
+/* stage 1 accepts with min{1, exp(-dEh)}, dEh an inexpensive estimate of dE; */
+/* a stage-1 pass is then accepted with min{1, exp(-(dE - dEh))}.  With dEh   */
+/* antisymmetric in the move the product of the two keeps detailed balance.  */
+/* Here dEh = l_B (eps(phi(x~_i)) - eps(phi(x_i))): eps is a small MLP and    */
+/* phi the neighbour-distance histograms of a position, built from the        */
+/* current positions of all other ions.                                       */
+/*                                                                            */
+/* Readings (listed in the design notes):                                     */
+/*  - phi(p): 64 bins of width rc/64 over r = |p - x_j| < rc, j != i, one      */
+/*    histogram for like-charged j (q_i q_j > 0), one for unlike-charged j    */
+/*    (q_i q_j < 0); r from the squared distance summed in double with no     */
+/*    fused multiply-add, bin = floor(r / (rc / 64)).                          */
+/*  - eps: 128 -> 128 -> 128 -> 1, ReLU, weights held at bfloat16 values;     */
+/*    each hidden activation is rounded to bfloat16 (round to nearest even)    */
+/*    before it feeds the next layer.                                         */
+/*  - stage 1 uses the move's accept uniform u3 (Philox word 3, tag 0);       */
+/*    stage 2 uses word 0 of the Philox block with tag 2.                     */
+/*  - conflict rule: ion i's move uses the plain Metropolis test instead when */
+/*    an ion j with a pending decision -- an ion of the `band` 64-ion groups  */
+/*    before i's group in the chain's sequence of groups, or of i's own group */
+/*    with j < i -- has its old or its trial position within rc of x_i or     */
+/*    x~_i.  The rule is symmetric in the move (it depends on the unordered   */
+/*    pair {x_i, x~_i}), so every move still satisfies detailed balance; for  */
+/*    all other moves phi is final when it is evaluated.  Groups before the   */
+/*    chain's first group do not exist.                                       */
+/* ======================================================================== */
+#define DA_BINS 64
+#define DA_IN (2 * DA_BINS)
+#define DA_HID 128
+#define DA_NPARAM (DA_IN * DA_HID + DA_HID + DA_HID * DA_HID + DA_HID + DA_HID + 1)
+
+int32_t orc_da_nparam(void) { return DA_NPARAM; }
+
+/* Round to the nearest bfloat16 (ties to even), through float. */
+static double bf16_round(double v)
+{
+    float f = (float)v;
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    b &= 0xFFFF0000u;
+    memcpy(&f, &b, 4);
+    return (double)f;
+}
+
+double orc_bf16_round(double v) { return bf16_round(v); }
+
+/* phi(p) for ion i: out[0..63] like-charged, out[64..127] unlike-charged. */
+void orc_da_features(int32_t n, const double* xyz, const double* q, int32_t i,
+                     const double* p, double rc, int32_t* out)
+{
+    double dr = rc / (double)DA_BINS;
+    for (int k = 0; k < DA_IN; ++k) out[k] = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double qq = q[i] * q[j];
+        if (qq == 0.0) continue;
+        double d2 = dist2(p, xyz + 3 * j);
+        if (!(d2 < rc * rc)) continue;
+        int32_t k = (int32_t)floor(sqrt(d2) / dr);
+        if (k >= DA_BINS) continue;
+        out[(qq > 0.0 ? 0 : DA_BINS) + k] += 1;
+    }
+}
+
+/*
+ * eps(phi) with params = [W1 (128 x 128, row = input), b1 (128),
+ * W2 (128 x 128, row = input), b2 (128), w3 (128), b3]; sums in double.
+ */
+double orc_mlp_eps(const double* params, const int32_t* feat)
+{
+    const double* W1 = params;
+    const double* b1 = W1 + DA_IN * DA_HID;
+    const double* W2 = b1 + DA_HID;
+    const double* b2 = W2 + DA_HID * DA_HID;
+    const double* w3 = b2 + DA_HID;
+    const double b3 = w3[DA_HID];
+    double h1[DA_HID], h2[DA_HID];
+    for (int h = 0; h < DA_HID; ++h) {
+        double z = b1[h];
+        for (int k = 0; k < DA_IN; ++k) z += (double)feat[k] * W1[k * DA_HID + h];
+        h1[h] = bf16_round(z > 0.0 ? z : 0.0);
+    }
+    for (int h = 0; h < DA_HID; ++h) {
+        double z = b2[h];
+        for (int k = 0; k < DA_HID; ++k) z += h1[k] * W2[k * DA_HID + h];
+        h2[h] = bf16_round(z > 0.0 ? z : 0.0);
+    }
+    double out = b3;
+    for (int k = 0; k < DA_HID; ++k) out += h2[k] * w3[k];
+    return out;
+}
+
+static int within(const double* a, const double* b, double rc)
+{
+    return dist2(a, b) < rc * rc;
+}
+
+/*
+ * DA chain over n_moves moves (move m = ion m % n of sweep sweep0 + m / n)
+ * in the chain's own sequence of 64-ion groups.  f32 != 0: the state is
+ * float (xyz holds float values) and trials are formed in float as in
+ * orc_replay_f32; otherwise as in orc_sweeps_f64.  With acc_given the
+ * trajectory follows the given decisions (a replay); otherwise this
+ * oracle's own decisions.  da_on == 0 gives the plain test for every move.
+ * Per move (first out_cap moves; outputs nullable): dE, dEh (0 for conflict
+ * moves), flags (bit0 wall, bit1 overlap, bit2 conflict, bit3 stage-1
+ * rejection, bit4 stage-2 rejection -- of the oracle's own evaluation),
+ * own decision, features [256] (phi(x_i), phi(x~_i); conflict moves too),
+ * u3 and u2.  eval_mask (nullable) limits the evaluation to marked moves
+ * (replays only).  *e_run accumulates accepted dE.  Returns the number of
+ * evaluated moves whose given decision differs from the oracle's, or -1 if
+ * a band > 0 replay does not start at sweep 0 (the pending trials of the
+ * previous sweep are not known), -2 on allocation failure.
+ */
+int64_t orc_da_run(int32_t n, double* xyz, const double* q, const double* sigma,
+                   double R, double lB, double D, uint64_t seed, uint32_t chain,
+                   uint32_t sweep0, int64_t n_moves, int32_t f32, const double* params,
+                   double rc, int32_t band, int32_t da_on, const uint8_t* acc_given,
+                   const uint8_t* eval_mask, int64_t out_cap, double* de_out,
+                   double* deh_out, uint8_t* flags_out, uint8_t* own_out,
+                   int32_t* feat_out, double* u3_out, double* u2_out, double* e_run)
+{
+    if (band > 0 && sweep0 != 0) return -1;
+    const int32_t group = 64;
+    const int32_t nb = (n + group - 1) / group;
+    /* latest old and trial position of every ion */
+    double* old = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* tri = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!old || !tri) {
+        free(old);
+        free(tri);
+        return -2;
+    }
+    int64_t mismatches = 0;
+    for (int64_t m = 0; m < n_moves; ++m) {
+        int32_t i = (int32_t)(m % n);
+        uint32_t sweep = sweep0 + (uint32_t)(m / n);
+        uint32_t w[4], w2[4];
+        move_words(seed, chain, sweep, (uint32_t)i, 0u, w);
+        move_words(seed, chain, sweep, (uint32_t)i, 2u, w2);
+        double xt[3];
+        if (f32) {
+            float Df = (float)D;
+            for (int k = 0; k < 3; ++k) {
+                float u = (float)(w[k] >> 8) * 0x1p-24f;
+                float t = u - 0.5f;
+                t = Df * t;
+                xt[k] = (double)((float)xyz[3 * i + k] + t);
+            }
+        } else {
+            trial_f64(xyz + 3 * i, w, D, xt);
+        }
+        const double* xi = xyz + 3 * i;
+        double u3 = (double)w[3] * 0x1p-32;
+        double u2 = (double)w2[0] * 0x1p-32;
+        int evaluate = !acc_given || !eval_mask || eval_mask[m];
+        int own = 0, flags = 0;
+        double dE = 0.0, deh = 0.0;
+        int32_t fo[DA_IN], fn[DA_IN];
+        if (evaluate) {
+            int wall = outside_wall(xt, R, sigma[i]);
+            int ov = 0;
+            dE = orc_delta_energy(n, xyz, q, sigma, i, xt, lB, &ov);
+            /* conflict: pending ions near x_i or x~_i in either of their positions */
+            int conflict = 0;
+            int64_t g = (int64_t)sweep * nb + i / group;
+            for (int64_t gp = g - band; gp <= g && !conflict; ++gp) {
+                if (gp < 0) continue;
+                int32_t bp = (int32_t)(gp % nb);
+                int32_t j0 = bp * group, j1 = j0 + group < n ? j0 + group : n;
+                if (gp == g) j1 = i;  /* own group: j < i */
+                for (int32_t j = j0; j < j1 && !conflict; ++j)
+                    conflict = within(xi, old + 3 * j, rc) || within(xi, tri + 3 * j, rc) ||
+                               within(xt, old + 3 * j, rc) || within(xt, tri + 3 * j, rc);
+            }
+            orc_da_features(n, xyz, q, i, xi, rc, fo);
+            orc_da_features(n, xyz, q, i, xt, rc, fn);
+            int s1 = 1, s2 = 1;
+            if (da_on && !conflict) {
+                deh = lB * (orc_mlp_eps(params, fn) - orc_mlp_eps(params, fo));
+                s1 = metropolis(deh, u3);
+                s2 = metropolis(dE - deh, u2);
+                own = !wall && !ov && s1 && s2;
+            } else {
+                own = !wall && !ov && metropolis(dE, u3);
+            }
+            flags = wall | (ov << 1) | (conflict << 2) | ((!s1) << 3) | ((s1 && !s2) << 4);
+        }
+        int acc = acc_given ? (int)acc_given[m] : own;
+        if (evaluate && acc != own) ++mismatches;
+        if (m < out_cap) {
+            if (de_out) de_out[m] = dE;
+            if (deh_out) deh_out[m] = deh;
+            if (flags_out) flags_out[m] = (uint8_t)flags;
+            if (own_out) own_out[m] = (uint8_t)own;
+            if (u3_out) u3_out[m] = u3;
+            if (u2_out) u2_out[m] = u2;
+            if (feat_out && evaluate)
+                for (int k = 0; k < DA_IN; ++k) {
+                    feat_out[m * 2 * DA_IN + k] = fo[k];
+                    feat_out[m * 2 * DA_IN + DA_IN + k] = fn[k];
+                }
+        }
+        for (int k = 0; k < 3; ++k) {
+            old[3 * i + k] = xi[k];
+            tri[3 * i + k] = xt[k];
+        }
+        if (acc) {
+            if (e_run) *e_run += dE;
+            for (int k = 0; k < 3; ++k) xyz[3 * i + k] = xt[k];
+        }
+    }
+    free(old);
+    free(tri);
+    return mismatches;
+}

@@ -80,6 +80,22 @@ def lib():
                                      ctypes.c_double, ctypes.c_double, ctypes.c_int32, _u64p,
                                      _u64p]
         L.orc_rdf_counts.restype = None
+        L.orc_da_nparam.argtypes = []
+        L.orc_da_nparam.restype = ctypes.c_int32
+        L.orc_bf16_round.argtypes = [ctypes.c_double]
+        L.orc_bf16_round.restype = ctypes.c_double
+        L.orc_da_features.argtypes = [ctypes.c_int32, _f64p, _f64p, ctypes.c_int32, _f64p,
+                                      ctypes.c_double, _i32p]
+        L.orc_da_features.restype = None
+        L.orc_mlp_eps.argtypes = [_f64p, _i32p]
+        L.orc_mlp_eps.restype = ctypes.c_double
+        L.orc_da_run.argtypes = [ctypes.c_int32, _f64p, _f64p, _f64p, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                 ctypes.c_uint32, ctypes.c_int64, ctypes.c_int32, _f64p,
+                                 ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _u8p, _u8p,
+                                 ctypes.c_int64, _f64p, _f64p, _u8p, _u8p, _i32p, _f64p, _f64p,
+                                 _f64p]
+        L.orc_da_run.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -287,3 +303,124 @@ def dh_log_ratio(r, lB, kappa, sigma):
     """
     r = np.asarray(r, np.float64)
     return 2.0 * lB * np.exp(-kappa * (r - sigma)) / (r * (1.0 + kappa * sigma))
+
+
+# --------------------------------------------------------------------------- #
+# Delayed acceptance with a learned first stage (two-stage Metropolis of      #
+# Christen and Fox 2005; not in the paper).  See mc_oracle.c for the          #
+# definitions of the features, the network and the conflict rule.            #
+# --------------------------------------------------------------------------- #
+
+DA_BINS, DA_IN, DA_HID = 64, 128, 128
+
+
+def da_nparam() -> int:
+    return int(lib().orc_da_nparam())
+
+
+def bf16(a):
+    """Round to the nearest bfloat16 value (ties to even), elementwise."""
+    a = np.asarray(a, np.float64)
+    f = a.astype(np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def unpack_params(params):
+    """Views (W1, b1, W2, b2, w3, b3) of the flat parameter vector."""
+    p = np.asarray(params, np.float64)
+    o = 0
+    W1 = p[o:o + DA_IN * DA_HID].reshape(DA_IN, DA_HID); o += DA_IN * DA_HID
+    b1 = p[o:o + DA_HID]; o += DA_HID
+    W2 = p[o:o + DA_HID * DA_HID].reshape(DA_HID, DA_HID); o += DA_HID * DA_HID
+    b2 = p[o:o + DA_HID]; o += DA_HID
+    w3 = p[o:o + DA_HID]; o += DA_HID
+    return W1, b1, W2, b2, w3, p[o]
+
+
+def da_features(xyz, q, i, p, rc=4.0) -> np.ndarray:
+    x = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)
+    qq = np.ascontiguousarray(q, np.float64)
+    pp = np.ascontiguousarray(p, np.float64)
+    out = np.zeros(DA_IN, np.int32)
+    lib().orc_da_features(len(qq), _p(x, _f64p), _p(qq, _f64p), int(i), _p(pp, _f64p), rc, _p(out, _i32p))
+    return out
+
+
+def mlp_eps(params, feat) -> float:
+    pp = np.ascontiguousarray(params, np.float64)
+    f = np.ascontiguousarray(feat, np.int32)
+    return float(lib().orc_mlp_eps(_p(pp, _f64p), _p(f, _i32p)))
+
+
+def da_run(xyz, q, sigma, R, lB, D, seed, chain, sweep0, n_moves, params, rc=4.0, band=0, da_on=1,
+           f32=False, acc_given=None, eval_mask=None, features=False):
+    """DA chain (own decisions) or replay (``acc_given``); returns a dict with
+    the final state ``x`` and per-move dE, dEh, flags, own, u3, u2 (and
+    features [n_moves, 256] if asked)."""
+    x = np.array(xyz, np.float64).reshape(-1, 3).copy()
+    if f32:
+        x = x.astype(np.float32).astype(np.float64)
+    qq = np.ascontiguousarray(q, np.float64)
+    ss = np.ascontiguousarray(sigma, np.float64)
+    pp = np.ascontiguousarray(params, np.float64)
+    m = int(n_moves)
+    de = np.zeros(m); deh = np.zeros(m); u3 = np.zeros(m); u2 = np.zeros(m)
+    fl = np.zeros(m, np.uint8); own = np.zeros(m, np.uint8)
+    feat = np.zeros((m, 2 * DA_IN), np.int32) if features else None
+    ag = None if acc_given is None else np.ascontiguousarray(acc_given, np.uint8)
+    em = None if eval_mask is None else np.ascontiguousarray(eval_mask, np.uint8)
+    e = ctypes.c_double(0.0)
+    mism = lib().orc_da_run(len(qq), _p(x, _f64p), _p(qq, _f64p), _p(ss, _f64p), R, lB, D, seed, chain,
+                            sweep0, m, 1 if f32 else 0, _p(pp, _f64p), rc, band, da_on, _p(ag, _u8p),
+                            _p(em, _u8p), m, _p(de, _f64p), _p(deh, _f64p), _p(fl, _u8p), _p(own, _u8p),
+                            _p(feat, _i32p), _p(u3, _f64p), _p(u2, _f64p), ctypes.byref(e))
+    if mism < 0:
+        raise ValueError("orc_da_run failed (%d)" % mism)
+    return {"x": x, "dE": de, "dEh": deh, "flags": fl, "own": own, "u3": u3, "u2": u2,
+            "features": feat, "mismatches": int(mism), "e_change": e.value}
+
+
+def mlp_forward(params, X, rounding=True):
+    """eps over the rows of X [rows, 128] in double, hidden activations
+    rounded to bfloat16 as in orc_mlp_eps (rounding=False: not rounded);
+    returns (out, cache)."""
+    W1, b1, W2, b2, w3, b3 = unpack_params(params)
+    X = np.asarray(X, np.float64)
+    rnd = bf16 if rounding else (lambda a: a)
+    Z1 = X @ W1 + b1
+    H1 = rnd(np.maximum(Z1, 0.0))
+    Z2 = H1 @ W2 + b2
+    H2 = rnd(np.maximum(Z2, 0.0))
+    out = H2 @ w3 + b3
+    return out, (X, Z1, H1, Z2, H2)
+
+
+def mlp_loss_grad(params, Xo, Xn, y, rounding=True):
+    """Loss L = mean((eps(Xn) - eps(Xo) - y)^2) over the batch and its
+    gradient with respect to the flat parameters, by backpropagation in
+    double (the bfloat16 rounding of the activations is passed through
+    unchanged by the derivative)."""
+    W1, b1, W2, b2, w3, b3 = unpack_params(params)
+    on, cn = mlp_forward(params, Xn, rounding)
+    oo, co = mlp_forward(params, Xo, rounding)
+    r = on - oo - np.asarray(y, np.float64)
+    B = len(r)
+    loss = float(np.mean(r * r))
+    d = 2.0 * r / B
+    g = np.zeros(len(params))
+    gW1 = np.zeros_like(W1); gb1 = np.zeros_like(b1); gW2 = np.zeros_like(W2); gb2 = np.zeros_like(b2)
+    gw3 = np.zeros_like(w3); gb3 = 0.0
+    for sign, (X, Z1, H1, Z2, H2) in ((1.0, cn), (-1.0, co)):
+        dout = sign * d
+        gw3 += H2.T @ dout
+        gb3 += float(np.sum(dout))
+        dZ2 = np.outer(dout, w3) * (Z2 > 0)
+        gW2 += H1.T @ dZ2
+        gb2 += dZ2.sum(0)
+        dZ1 = (dZ2 @ W2.T) * (Z1 > 0)
+        gW1 += X.T @ dZ1
+        gb1 += dZ1.sum(0)
+    g[:] = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gw3, [gb3]])
+    return loss, g

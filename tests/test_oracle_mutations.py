@@ -7,7 +7,9 @@ Eq. Delta E_ij), the wall radius without the ion's radius (Sec. 5.2), the
 contact distance of one ion instead of the additive one, a wrong Metropolis
 exponent (Eq. trial-outcome), an off-centre displacement (Alg. 1), a dropped
 Bjerrum length, a wrong Weyl constant or counter order of Philox4x32-10, and
-the overlap tested on the old instead of the trial position (Sec. 3.3).
+the overlap tested on the old instead of the trial position (Sec. 3.3); and
+in the delayed-acceptance stage a shifted feature bin, a dropped ReLU and
+bfloat16 rounding with ties away from zero.
 """
 from __future__ import annotations
 
@@ -31,6 +33,9 @@ MUTATIONS = [
     ("Philox Weyl constant", "#define PHILOX_W1 0xBB67AE85u", "#define PHILOX_W1 0xBB67AE86u"),
     ("Philox counter order", "uint32_t ctr[4] = {i, sweep, chain, tag};", "uint32_t ctr[4] = {sweep, i, chain, tag};"),
     ("overlap on old position", "if (d2t < sij * sij) ov = 1;", "if (d2 < sij * sij) ov = 1;"),
+    ("feature bin offset", "int32_t k = (int32_t)floor(sqrt(d2) / dr);", "int32_t k = (int32_t)ceil(sqrt(d2) / dr);"),
+    ("second ReLU dropped", "h2[h] = bf16_round(z > 0.0 ? z : 0.0);", "h2[h] = bf16_round(z);"),
+    ("bfloat16 ties away", "b += 0x7FFFu + ((b >> 16) & 1u);", "b += 0x8000u;"),
 ]
 
 
@@ -49,9 +54,11 @@ def _run_mutant(tmp_root, name, old, new):
         return name, "not applied"
     with open(src, "w") as f:
         f.write(text.replace(old, new))
-    r = subprocess.run([sys.executable, "-m", "pytest", "tests/test_oracle_pins.py", "-x", "-q",
+    r = subprocess.run([sys.executable, "-m", "pytest", "tests/test_oracle_pins.py", "tests/test_oracle_da_pins.py",
+                        "-x", "-q",
                         "-p", "no:cacheprovider", "-m", "not gpu and not slow"],
-                       cwd=d, capture_output=True, text=True, timeout=600)
+                       cwd=d, capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1"))
     return name, ("caught" if r.returncode == 1 else "survived rc=%d" % r.returncode)
 
 
