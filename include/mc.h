@@ -97,6 +97,15 @@ typedef struct mc_options {
     double wait_timeout_s;  /* limit of any single device-side wait, default 20   */
     int32_t record_timing;  /* nonzero: time every sweep-kernel launch with HIP
                                events on the handle's stream (see mc_timing)     */
+    /* delayed acceptance (see mc_set_surrogate) */
+    double da_rcut;         /* range of the neighbour histograms, default 4       */
+    int32_t da_window;      /* drift-monitor window in sweeps, default 10         */
+    double da_delta;        /* fall back to the plain test when a window's stage-2
+                               rejection rate exceeds the reference by more than
+                               this, default 0.05                                  */
+    int64_t log_moves;      /* log features, dE and dEh of the first this many
+                               moves of every chain for training (mc_get_log),
+                               0 = off                                             */
 } mc_options;
 
 /* Fills *opt with the defaults.  Returns MC_E_ARG if opt is NULL. */
@@ -196,7 +205,14 @@ typedef struct mc_stats {
     int32_t band;            /* band width used                                    */
     int32_t waves;           /* waves per workgroup used                           */
     int32_t workgroups;      /* workgroups used by the last sweep launch           */
-    int32_t reserved;
+    int32_t da_active;       /* delayed acceptance currently on                    */
+    int64_t da_moves;        /* moves decided by the two-stage test                */
+    int64_t da_conflicts;    /* moves that took the plain test by the conflict rule */
+    int64_t da_stage1_rejected;  /* two-stage moves rejected by stage 1           */
+    int64_t da_stage1_passed;    /* stage-1 passes without wall or overlap         */
+    int64_t da_stage2_rejected;  /* of those, rejected by stage 2                  */
+    int64_t da_fallback_sweep;   /* sweep of the fall-back to the plain test, -1   */
+    double da_last_rate;     /* stage-2 rejection rate of the last monitor window  */
 } mc_stats;
 
 /* Synchronises and fills *out. */
@@ -298,6 +314,54 @@ int mc_chain_launch_ms(mc_handle* h, double* ms);
  * finishes last).  model [2] (nullable) receives the fit.
  */
 int mc_autotune(mc_handle* h, int32_t calib_sweeps, uint64_t seed, double* model);
+
+/* ------------------------------------------------------------------------
+ * Delayed acceptance with a learned first stage (not in the paper; the
+ * two-stage Metropolis rule of Christen and Fox, 2005, with the paper's exact
+ * dE as the second stage, so the sampled distribution is unchanged).
+ *
+ * Stage 1 accepts with min{1, exp(-dEh)}, dEh = l_B (eps(phi(x~_i)) -
+ * eps(phi(x_i))), using the move's u3; a pass is accepted with
+ * min{1, exp(-(dE - dEh))}, using word 0 of the Philox block with tag 2.
+ * phi(p): 64-bin histograms (bin width rcut/64) of the distances r < rcut
+ * from p to the like-charged and to the unlike-charged other ions, at their
+ * current positions (128 inputs).  eps: 128 -> 128 -> 128 -> 1 with ReLU,
+ * bfloat16 weights, float sums, hidden activations rounded to bfloat16.
+ * Conflict rule: a move whose old or trial position lies within rcut of the
+ * old or trial position of an ion whose decision is still pending (the
+ * previous 64-ion group of the chain's sequence of groups, or a lower ion of
+ * its own group) takes the plain test; the rule depends on the unordered
+ * pair {x_i, x~_i} only, so detailed balance holds move by move.
+ * Surrogate chains use one band group (band 1).
+ * ------------------------------------------------------------------------ */
+
+/* Number of network parameters: W1 [128 x 128] (row = input), b1 [128],
+ * W2 [128 x 128], b2 [128], w3 [128], b3. */
+#define MC_DA_NPARAM 33153
+
+/*
+ * Installs the network on chain `chain` (-1: every chain) and switches its
+ * delayed acceptance on (active != 0) or off.  params [MC_DA_NPARAM] are
+ * rounded to bfloat16.  ref_stage2_reject is the stage-2 rejection rate of
+ * stage-1 passes measured when the network was trained (< 0: no drift
+ * monitor); the monitor compares each window of opt.da_window sweeps against
+ * ref + opt.da_delta and switches the chain to the plain test for good on the
+ * first window above it.  Needs 4 waves per workgroup.
+ */
+int mc_set_surrogate(mc_handle* h, int32_t chain, const double* params, double ref_stage2_reject,
+                     int32_t active);
+
+/*
+ * Synchronises and copies the training log of chain `chain` (opt.log_moves):
+ * for the first n moves, feats [n*256] byte histograms (phi(x_i) then
+ * phi(x~_i), each like-charged bins then unlike-charged), dE [n], dEh [n]
+ * (0 where the surrogate was not evaluated) and flags [n] (bit0 wall,
+ * bit1 overlap, bit2 conflict, bit3 stage-1 rejection, bit4 stage-2
+ * rejection, bit5 accepted, bit7 set for every logged move).  Any output may
+ * be NULL.
+ */
+int mc_get_log(mc_handle* h, int32_t chain, int64_t n, uint8_t* feats, double* dE, double* dEh,
+               uint8_t* flags);
 
 /* Releases every resource of the handle; NULL is allowed. */
 void mc_destroy(mc_handle* h);

@@ -432,8 +432,9 @@ static int within(const double* a, const double* b, double rc)
  * u3 and u2.  eval_mask (nullable) limits the evaluation to marked moves
  * (replays only).  *e_run accumulates accepted dE.  Returns the number of
  * evaluated moves whose given decision differs from the oracle's, or -1 if
- * a band > 0 replay does not start at sweep 0 (the pending trials of the
- * previous sweep are not known), -2 on allocation failure.
+ * a DA run with band > 0 does not start at sweep 0 (the pending trials of
+ * the previous sweep are not known; with DA off the conflict flags of the
+ * first band groups are then only indicative), -2 on allocation failure.
  */
 int64_t orc_da_run(int32_t n, double* xyz, const double* q, const double* sigma,
                    double R, double lB, double D, uint64_t seed, uint32_t chain,
@@ -443,7 +444,7 @@ int64_t orc_da_run(int32_t n, double* xyz, const double* q, const double* sigma,
                    double* deh_out, uint8_t* flags_out, uint8_t* own_out,
                    int32_t* feat_out, double* u3_out, double* u2_out, double* e_run)
 {
-    if (band > 0 && sweep0 != 0) return -1;
+    if (band > 0 && sweep0 != 0 && da_on) return -1;
     const int32_t group = 64;
     const int32_t nb = (n + group - 1) / group;
     /* latest old and trial position of every ion */
@@ -454,6 +455,9 @@ int64_t orc_da_run(int32_t n, double* xyz, const double* q, const double* sigma,
         free(tri);
         return -2;
     }
+    /* before its first move in this run an ion's pending positions are its current one */
+    memcpy(old, xyz, sizeof(double) * 3 * (size_t)n);
+    memcpy(tri, xyz, sizeof(double) * 3 * (size_t)n);
     int64_t mismatches = 0;
     for (int64_t m = 0; m < n_moves; ++m) {
         int32_t i = (int32_t)(m % n);

@@ -86,8 +86,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 }
 
 __device__ __forceinline__ uint4 move_words(uint64_t seed, uint32_t chain, uint32_t sweep,
-                                            uint32_t ion) {
-    return philox4x32_10(make_uint4(ion, sweep, chain, 0u), (uint32_t)seed, (uint32_t)(seed >> 32));
+                                            uint32_t ion, uint32_t tag = 0u) {
+    return philox4x32_10(make_uint4(ion, sweep, chain, tag), (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
 // Trial coordinate x + D (u - 1/2) (Sec. 3.2, Algorithm 1), every step rounded

@@ -33,9 +33,11 @@ namespace {
 thread_local std::string g_create_error = "no error";
 
 // Stats slots written by the sweep kernel.
-enum { ST_MOVES = 0, ST_ACC, ST_WALL, ST_OVERLAP, ST_METRO, ST_ITERS, ST_EARLY, ST_N };
+enum { ST_MOVES = 0, ST_ACC, ST_WALL, ST_OVERLAP, ST_METRO, ST_ITERS, ST_EARLY,
+       ST_DA_MOVES, ST_DA_CONFLICTS, ST_DA_S1REJ, ST_DA_S1PASS, ST_DA_S2REJ, ST_N };
 
 constexpr int64_t kMaxLaunchSweeps = 4096;
+static_assert(kDaParams == MC_DA_NPARAM, "network size differs from the header");
 // Default cost model of a chain (microseconds): per-sweep time
 // t(nb, w) = a nb + b nb^2 / w for nb groups of 64 served by w workgroups.
 constexpr double kModelA = 2.5, kModelB = 0.7;
@@ -69,12 +71,17 @@ bool device_info(DeviceInfo& di, std::string& err) {
 
 using SweepFn = void (*)(const ChainDesc*, const int2*, uint32_t, int32_t, Ctl);
 
-template <typename T, int M, bool U>
+template <typename T, int M, bool U, bool DA = false>
 SweepFn sweep_fn() {
-    return sweep_kernel<T, M, U>;
+    return sweep_kernel<T, M, U, DA>;
 }
 
-SweepFn pick_sweep(bool fp64, int waves, bool uniform) {
+// The delayed-acceptance kernels exist for 4 waves per workgroup.
+SweepFn pick_sweep(bool fp64, int waves, bool uniform, bool da = false) {
+    if (da) {
+        if (fp64) return uniform ? sweep_fn<double, 4, true, true>() : sweep_fn<double, 4, false, true>();
+        return uniform ? sweep_fn<float, 4, true, true>() : sweep_fn<float, 4, false, true>();
+    }
     if (fp64) {
         if (waves == 8) return uniform ? sweep_fn<double, 8, true>() : sweep_fn<double, 8, false>();
         return uniform ? sweep_fn<double, 4, true>() : sweep_fn<double, 4, false>();
@@ -119,6 +126,14 @@ struct Chain {
     int64_t e_capacity = 0;
     double* de_group = nullptr;   // grows: [n_sweeps * nb] of one launch
     int64_t de_capacity = 0;
+    // delayed acceptance
+    DAState* da = nullptr;        // arena
+    float* da_w = nullptr;        // [kDaParams], own allocation once installed
+    uint32_t* log_feat = nullptr; // [log_cap][64], own allocation
+    double* log_de = nullptr;
+    double* log_deh = nullptr;
+    uint8_t* log_flags = nullptr;
+    int64_t log_cap = 0;
     ChainDesc desc{};
 };
 
@@ -130,9 +145,12 @@ struct mc_handle {
     bool uniform_sigma = true;
     int waves = 4;
     int cap = 1;                  // co-resident workgroups of the sweep kernel
+    int cap_da = 0;               // ... of the delayed-acceptance kernel (0: not available)
     int wg_total = 1;             // workgroups of the sweep launch
     int wg_budget = 1;            // workgroups the schedule may use
     double model_a = kModelA, model_b = kModelB;
+    bool da_kernel = false;       // sweep launches use the delayed-acceptance kernel
+    int da_window = 0;            // monitor window of the installed surrogates (0: none)
     mc_options opt{};
     DeviceInfo dev;
     hipStream_t stream = nullptr;
@@ -200,10 +218,14 @@ void drop_events(mc_handle* h) {
 void free_all(mc_handle* h) {
     drop_events(h);
     for (Chain& c : h->chains) {
-        if (c.e_series) (void)hipFree(c.e_series);
-        if (c.de_group) (void)hipFree(c.de_group);
-        c.e_series = nullptr;
-        c.de_group = nullptr;
+        void* own[] = {c.e_series, c.de_group, c.da_w, c.log_feat, c.log_de, c.log_deh, c.log_flags};
+        for (void* b : own)
+            if (b) (void)hipFree(b);
+        c.e_series = c.de_group = nullptr;
+        c.da_w = nullptr;
+        c.log_feat = nullptr;
+        c.log_de = c.log_deh = nullptr;
+        c.log_flags = nullptr;
     }
     if (h->arena) (void)hipFree(h->arena);
     h->arena = nullptr;
@@ -373,7 +395,8 @@ void plan_schedule(mc_handle* h, std::vector<int>& wg, std::vector<int2>& map) {
     using Item = std::pair<double, int>;
     std::priority_queue<Item> pq;
     for (int k = 0; k < nc; ++k) pq.emplace(chain_cost(h, h->chains[k], 1), k);
-    while (!pq.empty() && used < h->wg_budget) {
+    const int budget = h->da_kernel ? std::min(h->wg_budget, h->cap_da) : h->wg_budget;
+    while (!pq.empty() && used < budget) {
         const int k = pq.top().second;
         pq.pop();
         const Chain& c = h->chains[k];
@@ -430,6 +453,15 @@ void fill_desc(mc_handle* h) {
         d.rdf_rc = c.R - h->opt.rdf_rmax;
         d.rdf_counts = c.rdf_counts;
         d.rdf_centres = c.rdf_centres;
+        d.da_w = c.da_w;
+        d.da = c.da;
+        d.da_rc = h->opt.da_rcut;
+        d.da_dr = h->opt.da_rcut / (double)kDaBins;
+        d.log_feat = c.log_feat;
+        d.log_de = c.log_de;
+        d.log_deh = c.log_deh;
+        d.log_flags = c.log_flags;
+        d.log_cap = c.log_cap;
     }
 }
 
@@ -522,7 +554,7 @@ int launch_sweeps(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
         int rc = upload_desc(h);
         if (rc) return rc;
     }
-    SweepFn fn = pick_sweep(h->fp64, h->waves, h->uniform_sigma);
+    SweepFn fn = pick_sweep(h->fp64, h->waves, h->uniform_sigma, h->da_kernel);
     Ctl ctl;
     ctl.abort = h->abort_flag;
     ctl.timeout_ticks = (uint64_t)(h->opt.wait_timeout_s * h->dev.wall_clock_hz);
@@ -561,6 +593,8 @@ int sweep_all(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
         const int re = h->opt.resum_every, rd = h->opt.rdf_every;
         if (re > 0) step = std::min<int64_t>(step, re - h->sweeps % re);
         if (rd > 0) step = std::min<int64_t>(step, rd - h->sweeps % rd);
+        const int dw = h->da_window;  // the drift monitor judges at window ends
+        if (dw > 0) step = std::min<int64_t>(step, dw - h->sweeps % dw);
         int rc = launch_sweeps(h, step, seed);
         if (rc) return rc;
         left -= step;
@@ -626,7 +660,21 @@ int create_handle(int32_t n_chains, const mc_chain_spec* specs, const mc_options
         (fa.sharedSizeBytes > 64 * 1024 || fa.localSizeBytes > 0))
         per_cu = 1;
     h->cap = per_cu * h->dev.cus;
-    if (n_chains > h->cap) {
+    if (h->waves == 4) {
+        // co-residency of the delayed-acceptance kernel (schedules are re-planned
+        // for it when it is switched on)
+        SweepFn fd = pick_sweep(h->fp64, 4, h->uniform_sigma, true);
+        int pd = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pd, (const void*)fd, 256, 0) != hipSuccess || pd < 1) {
+            h->err = "occupancy query failed for the delayed-acceptance kernel";
+            return bail(MC_E_DEVICE);
+        }
+        if (hipFuncGetAttributes(&fa, (const void*)fd) == hipSuccess &&
+            (fa.sharedSizeBytes > 64 * 1024 || fa.localSizeBytes > 0))
+            pd = 1;
+        h->cap_da = pd * h->dev.cus;
+    }
+    if (n_chains > h->cap || (opt.log_moves > 0 && n_chains > h->cap_da)) {
         h->err = "more chains (" + std::to_string(n_chains) + ") than co-resident workgroups (" +
                  std::to_string(h->cap) + ")";
         return bail(MC_E_ARG);
@@ -669,6 +717,7 @@ int create_handle(int32_t n_chains, const mc_chain_spec* specs, const mc_options
         plan.add(&c.sweep_tot, sizeof(double) * kMaxLaunchSweeps);
         plan.add(&c.rdf_counts, sizeof(unsigned long long) * nt * nt * opt.rdf_bins);
         plan.add(&c.rdf_centres, sizeof(unsigned long long) * nt);
+        plan.add(&c.da, sizeof(DAState));
         if (c.trace_cap > 0) {
             plan.add(&c.trace_acc, (size_t)c.trace_cap);
             plan.add(&c.trace_de, sizeof(double) * c.trace_cap);
@@ -768,6 +817,32 @@ int create_handle(int32_t n_chains, const mc_chain_spec* specs, const mc_options
     }
     for (Chain& c : h->chains) {
         if ((rc = grow_buffer(h, &c.e_series, &c.e_capacity, 1024, false))) return bail(rc);
+        DAState z{};
+        z.fallback_sweep = -1;
+        z.ref_rate = -1.0;
+        z.last_rate = -1.0;
+        z.min_count = 64;
+        if (hipMemcpy(c.da, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) {
+            h->err = "upload failed";
+            return bail(MC_E_DEVICE);
+        }
+        if (opt.log_moves > 0) {
+            c.log_cap = opt.log_moves;
+            if ((rc = dalloc(h, &c.log_feat, sizeof(uint32_t) * 64 * (size_t)c.log_cap)) ||
+                (rc = dalloc(h, &c.log_de, sizeof(double) * c.log_cap)) ||
+                (rc = dalloc(h, &c.log_deh, sizeof(double) * c.log_cap)) ||
+                (rc = dalloc(h, &c.log_flags, (size_t)c.log_cap)))
+                return bail(rc);
+            if (hipMemset(c.log_flags, 0, (size_t)c.log_cap) != hipSuccess) {
+                h->err = "clearing the log failed";
+                return bail(MC_E_DEVICE);
+            }
+        }
+    }
+    if (opt.log_moves > 0) {
+        // logging runs the delayed-acceptance kernel (features), with its band of one group
+        h->da_kernel = true;
+        for (Chain& c : h->chains) c.band = std::min(c.band, 1);
     }
     std::vector<int> wg;
     std::vector<int2> map;
@@ -791,6 +866,11 @@ int check_options(const mc_options& opt) {
     if (opt.waves != 0 && opt.waves != 4 && opt.waves != 8) return fail(nullptr, MC_E_ARG, "waves must be 0, 4 or 8");
     if (opt.workgroups < 0 || opt.trace_moves < 0) return fail(nullptr, MC_E_ARG, "negative count");
     if (!is_finite(opt.wait_timeout_s) || opt.wait_timeout_s <= 0) return fail(nullptr, MC_E_ARG, "bad wait_timeout_s");
+    if (!is_finite(opt.da_rcut) || opt.da_rcut <= 0 || opt.da_window < 0 || !is_finite(opt.da_delta) ||
+        opt.da_delta < 0 || opt.log_moves < 0)
+        return fail(nullptr, MC_E_ARG, "bad delayed-acceptance options");
+    if (opt.log_moves > 0 && opt.waves == 8)
+        return fail(nullptr, MC_E_ARG, "move logging needs 4 waves per workgroup");
     return MC_OK;
 }
 
@@ -936,6 +1016,16 @@ int chain_stats(mc_handle* h, int32_t ci, mc_stats* out) {
     out->band = c->band;
     out->waves = h->waves;
     out->workgroups = c->wg;
+    DAState ds;
+    HIPCHECK(h, hipMemcpy(&ds, c->da, sizeof(ds), hipMemcpyDeviceToHost));
+    out->da_active = ds.active && c->da_w != nullptr ? 1 : 0;
+    out->da_moves = (int64_t)st[ST_DA_MOVES];
+    out->da_conflicts = (int64_t)st[ST_DA_CONFLICTS];
+    out->da_stage1_rejected = (int64_t)st[ST_DA_S1REJ];
+    out->da_stage1_passed = (int64_t)st[ST_DA_S1PASS];
+    out->da_stage2_rejected = (int64_t)st[ST_DA_S2REJ];
+    out->da_fallback_sweep = ds.fallback_sweep;
+    out->da_last_rate = ds.last_rate;
     return MC_OK;
 }
 
@@ -981,6 +1071,10 @@ int mc_options_init(mc_options* o) {
     o->workgroups = 0;
     o->trace_moves = 0;
     o->wait_timeout_s = 20.0;
+    o->da_rcut = 4.0;
+    o->da_window = 10;
+    o->da_delta = 0.05;
+    o->log_moves = 0;
     return MC_OK;
 }
 
@@ -1152,8 +1246,9 @@ int mc_set_schedule(mc_handle* h, const int32_t* workgroups) {
             return fail(h, MC_E_ARG, "chain " + std::to_string(k) + ": workgroups must be in [1, groups of 64]");
         total += workgroups[k];
     }
-    if (total > h->cap)
-        return fail(h, MC_E_ARG, "total workgroups exceed the co-resident capacity " + std::to_string(h->cap));
+    const int cap_now = h->da_kernel ? h->cap_da : h->cap;
+    if (total > cap_now)
+        return fail(h, MC_E_ARG, "total workgroups exceed the co-resident capacity " + std::to_string(cap_now));
     int rc = sync_check(h);
     if (rc) return rc;
     std::vector<int> wg(workgroups, workgroups + h->chains.size());
@@ -1234,6 +1329,74 @@ int mc_autotune(mc_handle* h, int32_t calib_sweeps, uint64_t seed, double* model
     plan_schedule(h, wg, map);
     if ((rc = apply_schedule(h, wg, map))) return rc;
     if (h->opt.resum_every > 0 && h->sweeps % h->opt.resum_every == 0 && (rc = launch_energy(h, 1, 1))) return rc;
+    return MC_OK;
+}
+
+int mc_set_surrogate(mc_handle* h, int32_t chain, const double* params, double ref_stage2_reject,
+                     int32_t active) {
+    if (!h) return MC_E_ARG;
+    if (!params) return fail(h, MC_E_ARG, "params is NULL");
+    if (chain < -1 || chain >= (int32_t)h->chains.size()) return fail(h, MC_E_ARG, "bad chain index");
+    if (h->waves != 4) return fail(h, MC_E_ARG, "delayed acceptance needs 4 waves per workgroup");
+    if (!is_finite(ref_stage2_reject)) return fail(h, MC_E_ARG, "ref_stage2_reject must be finite");
+    std::vector<float> w(kDaParams);
+    for (int k = 0; k < kDaParams; ++k) {
+        if (!is_finite(params[k])) return fail(h, MC_E_ARG, "non-finite network parameter");
+        float f = (float)params[k];
+        uint32_t b;
+        std::memcpy(&b, &f, 4);
+        b += 0x7FFFu + ((b >> 16) & 1u);
+        b &= 0xFFFF0000u;
+        std::memcpy(&f, &b, 4);
+        w[k] = f;
+    }
+    int rc = sync_check(h);
+    if (rc) return rc;
+    for (int32_t k = 0; k < (int32_t)h->chains.size(); ++k) {
+        if (chain >= 0 && k != chain) continue;
+        Chain& c = h->chains[k];
+        if (!c.da_w && (rc = dalloc(h, &c.da_w, sizeof(float) * kDaParams))) return rc;
+        HIPCHECK(h, hipMemcpy(c.da_w, w.data(), sizeof(float) * kDaParams, hipMemcpyHostToDevice));
+        unsigned long long st[ST_N];
+        HIPCHECK(h, hipMemcpy(st, c.stats, sizeof(st), hipMemcpyDeviceToHost));
+        DAState ds;
+        HIPCHECK(h, hipMemcpy(&ds, c.da, sizeof(ds), hipMemcpyDeviceToHost));
+        ds.active = active ? 1 : 0;
+        ds.window = h->opt.da_window;
+        ds.fallback_sweep = -1;
+        ds.ref_rate = ref_stage2_reject;
+        ds.delta = h->opt.da_delta;
+        ds.win_pass0 = st[ST_DA_S1PASS];
+        ds.win_rej0 = st[ST_DA_S2REJ];
+        ds.last_rate = -1.0;
+        ds.min_count = 64;
+        HIPCHECK(h, hipMemcpy(c.da, &ds, sizeof(ds), hipMemcpyHostToDevice));
+        c.band = std::min(c.band, 1);
+    }
+    h->da_window = h->opt.da_window;
+    if (!h->da_kernel) {
+        if ((int)h->chains.size() > h->cap_da)
+            return fail(h, MC_E_ARG, "more chains than co-resident workgroups of the delayed-acceptance kernel");
+        h->da_kernel = true;
+        std::vector<int> wg;
+        std::vector<int2> map;
+        plan_schedule(h, wg, map);
+        return apply_schedule(h, wg, map);
+    }
+    return upload_desc(h);
+}
+
+int mc_get_log(mc_handle* h, int32_t chain, int64_t n, uint8_t* feats, double* dE, double* dEh, uint8_t* flags) {
+    Chain* c = get_chain(h, chain);
+    if (!c) return h ? fail(h, MC_E_ARG, "bad chain index") : MC_E_ARG;
+    if (n < 0 || n > c->log_cap) return fail(h, MC_E_ARG, "n exceeds the log capacity");
+    int rc = sync_check(h);
+    if (rc) return rc;
+    if (n == 0) return MC_OK;
+    if (feats) HIPCHECK(h, hipMemcpy(feats, c->log_feat, sizeof(uint32_t) * 64 * (size_t)n, hipMemcpyDeviceToHost));
+    if (dE) HIPCHECK(h, hipMemcpy(dE, c->log_de, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (dEh) HIPCHECK(h, hipMemcpy(dEh, c->log_deh, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (flags) HIPCHECK(h, hipMemcpy(flags, c->log_flags, (size_t)n, hipMemcpyDeviceToHost));
     return MC_OK;
 }
 

@@ -45,6 +45,24 @@
 
 namespace mcdev {
 
+// Delayed-acceptance surrogate: sizes of the network and of its input.
+constexpr int kDaBins = 64;               // bins of each neighbour histogram
+constexpr int kDaIn = 2 * kDaBins;        // like- and unlike-charge histograms
+constexpr int kDaHid = 128;               // hidden units of both hidden layers
+constexpr int kDaParams = kDaIn * kDaHid + kDaHid + kDaHid * kDaHid + kDaHid + kDaHid + 1;
+
+// Device state of a chain's delayed-acceptance stage and its drift monitor.
+struct DAState {
+    int32_t active;          // 1: two-stage test for moves without a conflict
+    int32_t window;          // monitor window in sweeps (launches end on its multiples)
+    int64_t fallback_sweep;  // sweep at which the monitor switched to the plain test, -1 = never
+    double ref_rate;         // stage-2 rejection rate of stage-1 passes at training time (< 0: no monitor)
+    double delta;            // switch to the plain test when a window's rate exceeds ref_rate + delta
+    unsigned long long win_pass0, win_rej0;  // counters at the start of the window
+    double last_rate;        // rate of the last complete window
+    int64_t min_count;       // windows with fewer stage-1 passes are not judged
+};
+
 // Description of one chain inside a sweep launch (device memory).
 struct ChainDesc {
     int32_t n;           // ions
@@ -82,6 +100,17 @@ struct ChainDesc {
     double rdf_rc;       // centres need |x| <= rdf_rc
     unsigned long long* rdf_counts;   // [ntypes * ntypes * bins]
     unsigned long long* rdf_centres;  // [ntypes]
+    // delayed acceptance (kernels with DA = true only)
+    const float* da_w;   // [kDaParams] network parameters (bfloat16 values held in float)
+    DAState* da;         // monitor state
+    double da_rc;        // histogram range
+    double da_dr;        // histogram bin width da_rc / 64
+    uint32_t* log_feat;  // [log_cap][64] packed byte histograms of logged moves
+    double* log_de;      // [log_cap] exact dE
+    double* log_deh;     // [log_cap] surrogate dEh (0 when not evaluated)
+    uint8_t* log_flags;  // [log_cap] bit0 wall, 1 overlap, 2 conflict, 3 stage-1 reject,
+                         //           4 stage-2 reject, 5 accepted, 7 written
+    int64_t log_cap;     // moves logged from the start of the chain
 };
 
 // A position record is {x, y, z, version}: version = sweep index (mod 2^32)
@@ -172,10 +201,15 @@ template <int P> struct SliceBits;
 template <> struct SliceBits<8> { using type = uint8_t; };
 template <> struct SliceBits<16> { using type = uint16_t; };
 
-template <typename T, int M>
+// Band groups with candidate corrections in LDS: kMaxBand, or 1 for the
+// delayed-acceptance kernels (whose LDS also holds neighbour histograms).
+template <bool DA> constexpr int kBandSlots = DA ? 1 : kMaxBand;
+
+template <typename T, int M, bool DA = false>
 struct SweepShared {
     using T4 = typename Prec<T>::T4;
     static constexpr int P = kGroup / M;
+    static constexpr int KB = kBandSlots<DA>;
     using SB = typename SliceBits<P>::type;
     // per compute wave: staging of the current partner slice {x, y, z, q}
     T4 st_old[M][P];
@@ -188,15 +222,27 @@ struct SweepShared {
                                 // corrections still unknown (band groups, own group)
     SB ovo_own[M][kGroup];      // own group, j < i: overlap with j's old position
     SB ovt_own[M][kGroup];      //                   overlap with j's trial position
-    SB ovo_b[kMaxBand][M][kGroup];  // group g-1-kb: overlap with j's old / trial position
-    SB ovt_b[kMaxBand][M][kGroup];
+    SB ovo_b[KB][M][kGroup];    // group g-1-kb: overlap with j's old / trial position
+    SB ovt_b[KB][M][kGroup];
     // corrections, one padded row per mover i (16-byte reads of 4 partners
     // are free of bank conflicts)
     static constexpr int CS = kGroup + (sizeof(T) == 4 ? 4 : 2);
     T c_own[kGroup][CS];           // own group [mover i][partner j]
-    T c_b[kMaxBand][kGroup][CS];   // group g-1-kb [mover i][partner j]
+    T c_b[KB][kGroup][CS];         // group g-1-kb [mover i][partner j]
     int ready;                  // compute waves done filling the hand-off for the current target
     int consumed;               // local target index + 1 the chain wave last released
+    // delayed acceptance: per mover, byte histograms of neighbour distances at
+    // the old position (bytes 0..127) and at the trial position (128..255),
+    // each like-charged bins 0..63 then unlike-charged; conflict ballots of
+    // the waves; the surrogate's dEh; partial sums of the network's last layer
+    uint32_t hist[DA ? kGroup : 1][DA ? 65 : 1];   // rows padded to 65 words (bank-conflict free)
+    uint64_t part_conf[DA ? M : 1];
+    double deh[DA ? kGroup : 1];
+    float part_out[DA ? M : 1][2][DA ? kGroup : 1];
+    // bfloat16 hidden activations [mover][position][unit] of the network, in
+    // the space of c_own and c_b (free between the chain wave's release and
+    // the next hand-off)
+    __device__ uint16_t* h1() { return reinterpret_cast<uint16_t*>(&c_own[0][0]); }
 };
 
 // Bounded LDS wait used between the compute waves and the chain wave.
@@ -268,17 +314,21 @@ __device__ __forceinline__ void publish_group(__amdgpu_buffer_rsrc_t rec_r, __am
 // of the pair terms: combine the waves' hand-off, decide the group (from the
 // bounds, or after the band groups' accept masks by fixed-point iteration)
 // and publish.
-template <typename T, int M>
-__device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDesc& cd,
+// Counters of one workgroup, added to the chain's stats at the end.
+struct WgCounters {
+    unsigned long long moves = 0, acc = 0, wall = 0, ov = 0, iters = 0, early = 0;
+    unsigned long long da_moves = 0, conflicts = 0, s1_rej = 0, s2_rej = 0, s1_pass = 0;
+};
+
+template <typename T, int M, bool DA>
+__device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const ChainDesc& cd,
                                            __amdgpu_buffer_rsrc_t pos_r, __amdgpu_buffer_rsrc_t rec_r,
                                            const T* __restrict__ charge, int64_t g_begin, int64_t g, int t,
-                                           T xi, T yi, T zi, T txi, T tyi, T tzi, uint32_t w3,
-                                           const Ctl& ctl, unsigned long long& c_moves,
-                                           unsigned long long& c_acc, unsigned long long& c_wall,
-                                           unsigned long long& c_ov, unsigned long long& c_iters,
-                                           unsigned long long& c_early)
+                                           T xi, T yi, T zi, T txi, T tyi, T tzi, uint32_t w3, bool da_active,
+                                           const Ctl& ctl, WgCounters& ctr)
 {
     constexpr int P = kGroup / M;
+    constexpr int KB = SweepShared<T, M, DA>::KB;
     const int lane = threadIdx.x & 63;
     const int n = cd.n, nb = cd.nb, band = cd.band;
     const int npad = nb * kGroup;
@@ -309,11 +359,11 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
     tl1 = wall_clock64();
 #endif
     double St = 0.0;
-    uint64_t ovo = 0, ovt = 0, ovob[kMaxBand], ovtb[kMaxBand];
+    uint64_t ovo = 0, ovt = 0, ovob[KB], ovtb[KB];
     bool ovb = false;
     T cp = 0, cn = 0;
 #pragma unroll
-    for (int kb = 0; kb < kMaxBand; ++kb) ovob[kb] = ovtb[kb] = 0;
+    for (int kb = 0; kb < KB; ++kb) ovob[kb] = ovtb[kb] = 0;
 #pragma unroll
     for (int w = 0; w < M; ++w) {
         cp += sh.part_pn[w][0][lane];
@@ -323,9 +373,35 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
         ovo |= (uint64_t)sh.ovo_own[w][lane] << (w * P);
         ovt |= (uint64_t)sh.ovt_own[w][lane] << (w * P);
 #pragma unroll
-        for (int kb = 0; kb < kMaxBand; ++kb) {
+        for (int kb = 0; kb < KB; ++kb) {
             ovob[kb] |= (uint64_t)sh.ovo_b[kb][w][lane] << (w * P);
             ovtb[kb] |= (uint64_t)sh.ovt_b[kb][w][lane] << (w * P);
+        }
+    }
+
+    // Delayed acceptance (two-stage rule): a move without a conflict passes
+    // stage 1 when dEh <= 0 or u3 < exp(-dEh), i.e. dEh < thr, and is then
+    // accepted when dE - dEh <= 0 or u2 < exp(-(dE - dEh)), i.e. when
+    // dE <= dEh or dE < dEh - log(u2).  The plain rule is the special case
+    // shift = 0, thr_eff = thr; a stage-1 rejection sets both to -inf.
+    double shift = 0.0, thr_eff = thr, deh = 0.0;
+    bool conflict = false, da_lane = false, s1_rej = false;
+    if constexpr (DA) {
+        uint64_t cm = 0;
+#pragma unroll
+        for (int w = 0; w < M; ++w) cm |= sh.part_conf[w];
+        conflict = ((cm >> lane) & 1ull) != 0;
+        if (da_active && valid && !conflict) {
+            da_lane = true;
+            deh = sh.deh[lane];
+            if (deh <= 0.0 || deh < thr) {
+                const uint4 w2 = move_words(cd.seed, cd.chain_id, (uint32_t)s, (uint32_t)ion, 2u);
+                shift = deh;
+                thr_eff = deh - log(accept_uniform(w2.x));
+            } else {
+                s1_rej = true;
+                shift = thr_eff = -1.0e300;
+            }
         }
     }
 
@@ -356,13 +432,13 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
         const double margin = fabs(lq) * (1e-4 * span + 1e-9 * (fabs(St) + 1.0)) + 1e-12;
         uint64_t ov_sure = 0, ov_flip = ovo ^ ovt;
 #pragma unroll
-        for (int kb = 0; kb < kMaxBand; ++kb) {
+        for (int kb = 0; kb < KB; ++kb) {
             ov_sure |= ovob[kb] & ovtb[kb];
             ov_flip |= ovob[kb] ^ ovtb[kb];
         }
-        const bool reject_sure = !can || ov_sure != 0 || (ovo & ovt) != 0;
-        const bool accept_sure = !reject_sure && ov_flip == 0 && e_hi < thr - margin;
-        const bool sure = reject_sure || accept_sure || (ov_flip == 0 && e_lo >= thr + margin);
+        const bool reject_sure = !can || s1_rej || ov_sure != 0 || (ovo & ovt) != 0;
+        const bool accept_sure = !reject_sure && ov_flip == 0 && e_hi < thr_eff - margin;
+        const bool sure = reject_sure || accept_sure || (ov_flip == 0 && e_lo >= thr_eff + margin);
         if (__ballot(!sure) == 0ull) {
             early = true;
             acc = __ballot(accept_sure);
@@ -376,7 +452,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
     // band corrections, oldest group first
     double corr = 0.0;
 #pragma unroll
-    for (int kb = kMaxBand - 1; kb >= 0; --kb) {
+    for (int kb = KB - 1; kb >= 0; --kb) {
         if (kb < band) {
             const GroupRec r = wait_rec(rec_r, g - 1 - kb, ctl);
 #ifdef MC_TIMELINE
@@ -396,7 +472,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
         St += corr;
         const bool can2 = valid && !wall && !ovb;
         dE = lq * St;
-        dec = can2 && (dE <= 0.0 || dE < thr);
+        dec = can2 && (dE <= shift || dE < thr_eff);
         it = 1;
         uint64_t nacc = __ballot(dec);
         while (nacc != acc && it <= kGroup + 1) {
@@ -404,7 +480,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
             const T own = masked_row_sum<T>(sh.c_own[lane], acc);
             const bool ovown = ((acc & ovt) | (~acc & ovo)) != 0;
             dE = lq * (St + (double)own);
-            dec = can2 && !ovown && (dE <= 0.0 || dE < thr);
+            dec = can2 && !ovown && (dE <= shift || dE < thr_eff);
             nacc = __ballot(dec);
             ++it;
         }
@@ -449,32 +525,179 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M>& sh, const ChainDes
     if (lane == 0) cd.de_group[g - g_begin] = de_group;
     const uint64_t m_wall = __ballot(valid && wall);
     const uint64_t m_valid = __ballot(valid);
-    c_moves += __popcll(m_valid);
-    c_acc += __popcll(acc);
-    c_wall += __popcll(m_wall);
-    c_ov += __popcll(m_ov);
-    c_iters += it;
-    c_early += early ? 1 : 0;
+    ctr.moves += __popcll(m_valid);
+    ctr.acc += __popcll(acc);
+    ctr.wall += __popcll(m_wall);
+    ctr.ov += __popcll(m_ov);
+    ctr.iters += it;
+    ctr.early += early ? 1 : 0;
+    if constexpr (DA) {
+        const bool ov_final = ((m_ov >> lane) & 1ull) != 0;
+        const bool passed = da_lane && !s1_rej && !wall && !ov_final;
+        ctr.da_moves += __popcll(__ballot(da_lane));
+        ctr.conflicts += __popcll(__ballot(valid && conflict));
+        ctr.s1_rej += __popcll(__ballot(s1_rej));
+        ctr.s1_pass += __popcll(__ballot(passed));
+        ctr.s2_rej += __popcll(__ballot(passed && !dec));
+        const int64_t mv = s * (int64_t)n + ion;
+        if (valid && mv < cd.log_cap) {
+            cd.log_de[mv] = dE;
+            cd.log_deh[mv] = deh;
+            cd.log_flags[mv] = (uint8_t)(0x80u | (uint32_t)wall | ((uint32_t)ov_final << 1) |
+                                         ((uint32_t)conflict << 2) | ((uint32_t)s1_rej << 3) |
+                                         ((uint32_t)(passed && !dec) << 4) | ((uint32_t)dec << 5));
+        }
+    }
 }
 
 // Occupancy asked of the compiler (waves per SIMD): two workgroups per CU.
-template <typename T, int M>
-constexpr int kWavesPerEU = sizeof(T) == 4 ? (M == 8 ? 4 : 2) : 1;
+// (the delayed-acceptance kernels take one wave per SIMD: their register use
+// would otherwise spill; they run one workgroup per CU)
+template <typename T, int M, bool DA = false>
+constexpr int kWavesPerEU = DA ? 1 : (sizeof(T) == 4 ? (M == 8 ? 4 : 2) : 1);
 
-template <typename T, int M, bool UNIFORM_SIGMA>
+// Squared distance in double, summed in the order x, y, z with no fused
+// multiply-add: the neighbour-histogram bins and the conflict rule of the
+// delayed-acceptance stage are decided on this value.
+__device__ __forceinline__ double d2_exact(double ax, double ay, double az, double bx, double by, double bz) {
+    const double dx = ax - bx, dy = ay - by, dz = az - bz;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Adds a neighbour at squared distance d2 to byte bin (pos, like/unlike, k)
+// of mover `lane`'s histogram (four byte counters per LDS word).
+template <typename SH>
+__device__ __forceinline__ void da_hist_add(SH& sh, const ChainDesc& cd, int lane, int pos, bool unlike, double d2) {
+    if (!(d2 < cd.da_rc * cd.da_rc)) return;
+    const int k = (int)__builtin_floor(__builtin_sqrt(d2) / cd.da_dr);
+    if (k >= kDaBins) return;
+    const int byte = pos * kDaIn + (unlike ? kDaBins : 0) + k;
+    atomicAdd(&sh.hist[lane][byte >> 2], 1u << (8 * (byte & 3)));
+}
+
+__device__ __forceinline__ float bf16_round(float v) {
+    uint32_t b = __builtin_bit_cast(uint32_t, v);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return __builtin_bit_cast(float, b & 0xFFFF0000u);
+}
+
+// Delayed-acceptance stage of one target group, run by all M waves between
+// the chain wave's release of the hand-off buffer and the next hand-off:
+// logs the movers' histograms, evaluates the network eps at both positions
+// of every mover (wave w computes hidden units [w U, (w + 1) U) of both
+// layers; sums in float, bfloat16 activations), leaves
+// dEh = l_B (eps(trial) - eps(old)) in sh.deh and clears the histograms.
+template <typename T, int M>
+__device__ __forceinline__ void da_network(SweepShared<T, M, true>& sh, const ChainDesc& cd, int wave, int lane,
+                                           bool da_on, int64_t mv, bool valid) {
+    constexpr int U = kDaHid / M;     // hidden units per wave
+    constexpr int WW = 64 / M;        // histogram words logged and cleared per wave
+    constexpr int H1S = 2 * kDaHid + 2;  // row stride in bfloat16 values (odd word stride)
+    static_assert(sizeof(sh.c_own) + sizeof(sh.c_b) >= sizeof(uint16_t) * kGroup * H1S,
+                  "hidden activations must fit in the candidate space");
+    __syncthreads();  // every histogram add of this target is done
+    if (valid && mv < cd.log_cap) {
+        uint32_t* dst = cd.log_feat + mv * 64;
+#pragma unroll
+        for (int k = 0; k < WW; ++k) dst[wave * WW + k] = sh.hist[lane][wave * WW + k];
+    }
+    uint16_t* h1 = sh.h1();
+    const float* W1 = cd.da_w;
+    const float* b1 = W1 + kDaIn * kDaHid;
+    const float* W2 = b1 + kDaHid;
+    const float* b2 = W2 + kDaHid * kDaHid;
+    const float* w3 = b2 + kDaHid;
+    constexpr int UC = 8;  // hidden units per pass (bounded register use)
+    if (da_on) {
+#pragma unroll 1
+        for (int hc = wave * U; hc < wave * U + U; hc += UC) {
+            float a0[UC], a1[UC];
+#pragma unroll
+            for (int u = 0; u < UC; ++u) a0[u] = a1[u] = b1[hc + u];
+#pragma unroll 2
+            for (int kw = 0; kw < kDaIn / 4; ++kw) {
+                const uint32_t f0w = sh.hist[lane][kw], f1w = sh.hist[lane][kDaIn / 4 + kw];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float f0 = (float)((f0w >> (8 * c)) & 0xFFu), f1 = (float)((f1w >> (8 * c)) & 0xFFu);
+                    const float* wr = W1 + (4 * kw + c) * kDaHid + hc;
+#pragma unroll
+                    for (int u = 0; u < UC; ++u) {
+                        a0[u] = __builtin_fmaf(f0, wr[u], a0[u]);
+                        a1[u] = __builtin_fmaf(f1, wr[u], a1[u]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UC; ++u) {
+                h1[lane * H1S + hc + u] =
+                    (uint16_t)(__builtin_bit_cast(uint32_t, bf16_round(a0[u] > 0.f ? a0[u] : 0.f)) >> 16);
+                h1[lane * H1S + kDaHid + hc + u] =
+                    (uint16_t)(__builtin_bit_cast(uint32_t, bf16_round(a1[u] > 0.f ? a1[u] : 0.f)) >> 16);
+            }
+        }
+    }
+    __syncthreads();  // first hidden layer complete
+#pragma unroll
+    for (int k = 0; k < WW; ++k) sh.hist[lane][wave * WW + k] = 0u;
+    if (da_on) {
+        float o0 = 0.f, o1 = 0.f;
+#pragma unroll 1
+        for (int hc = wave * U; hc < wave * U + U; hc += UC) {
+            float a0[UC], a1[UC];
+#pragma unroll
+            for (int u = 0; u < UC; ++u) a0[u] = a1[u] = b2[hc + u];
+#pragma unroll 2
+            for (int k = 0; k < kDaHid; k += 2) {
+                const uint32_t v0 = *reinterpret_cast<const uint32_t*>(&h1[lane * H1S + k]);
+                const uint32_t v1 = *reinterpret_cast<const uint32_t*>(&h1[lane * H1S + kDaHid + k]);
+                const float x0a = __builtin_bit_cast(float, v0 << 16), x0b = __builtin_bit_cast(float, v0 & 0xFFFF0000u);
+                const float x1a = __builtin_bit_cast(float, v1 << 16), x1b = __builtin_bit_cast(float, v1 & 0xFFFF0000u);
+                const float* wa = W2 + k * kDaHid + hc;
+                const float* wb = wa + kDaHid;
+#pragma unroll
+                for (int u = 0; u < UC; ++u) {
+                    a0[u] = __builtin_fmaf(x0b, wb[u], __builtin_fmaf(x0a, wa[u], a0[u]));
+                    a1[u] = __builtin_fmaf(x1b, wb[u], __builtin_fmaf(x1a, wa[u], a1[u]));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UC; ++u) {
+                o0 = __builtin_fmaf(bf16_round(a0[u] > 0.f ? a0[u] : 0.f), w3[hc + u], o0);
+                o1 = __builtin_fmaf(bf16_round(a1[u] > 0.f ? a1[u] : 0.f), w3[hc + u], o1);
+            }
+        }
+        sh.part_out[wave][0][lane] = o0;
+        sh.part_out[wave][1][lane] = o1;
+    }
+    __syncthreads();  // partial outputs complete; the candidate space is free again
+    if (da_on && wave == 0) {
+        const float b3 = cd.da_w[kDaParams - 1];
+        float o0 = b3, o1 = b3;
+#pragma unroll
+        for (int w = 0; w < M; ++w) {
+            o0 += sh.part_out[w][0][lane];
+            o1 += sh.part_out[w][1][lane];
+        }
+        sh.deh[lane] = cd.lB * ((double)o1 - (double)o0);
+    }
+}
+
+template <typename T, int M, bool UNIFORM_SIGMA, bool DA = false>
 __global__ void __launch_bounds__(64 * M)
-__attribute__((amdgpu_waves_per_eu(kWavesPerEU<T, M>)))
+__attribute__((amdgpu_waves_per_eu(kWavesPerEU<T, M, DA>)))
 sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_map,
              uint32_t s0, int32_t n_sweeps, Ctl ctl)
 {
     using T4 = typename Prec<T>::T4;
     using IO = PosIO<T>;
     constexpr int P = kGroup / M;
+    constexpr int KB = SweepShared<T, M, DA>::KB;
     using SB = typename SliceBits<P>::type;
-    __shared__ SweepShared<T, M> sh;
+    __shared__ SweepShared<T, M, DA> sh;
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // workgroup -> (chain, index of the workgroup among the chain's)
     const int2 wm = wg_map[blockIdx.x];
     const ChainDesc& cd = chains[wm.x];
@@ -496,9 +719,16 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
         sh.consumed = 0;
         if (k_wg == 0) cd.clk[0] = wall_clock64();
     }
+    if constexpr (DA) {
+        static_assert(sizeof(sh.hist) == sizeof(uint32_t) * kGroup * 65, "histogram rows");
+        for (int k = threadIdx.x; k < kGroup * 65; k += 64 * M) (&sh.hist[0][0])[k] = 0u;
+    }
+    // the delayed-acceptance switch is constant during a launch (the drift
+    // monitor changes it between launches)
+    const bool da_on = DA && cd.da != nullptr && cd.da->active != 0 && cd.da_w != nullptr;
     __syncthreads();
 
-    unsigned long long c_moves = 0, c_acc = 0, c_wall = 0, c_ov = 0, c_iters = 0, c_early = 0;
+    WgCounters ctr;
     {
         int t = 0;
         for (int64_t g = g_begin + k_wg; g < g_end; g += cd.wg_count, ++t) {
@@ -517,6 +747,7 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
 
             double S = 0.0;     // sum_j q_j (1/|x~_i - x_j| - 1/|x_i - x_j|)
             bool ov = false;    // overlap with a partner whose position is final
+            bool conf = false;  // delayed acceptance: a pending partner is near (conflict rule)
 
             // ---- own group: both outcomes of every partner j != i
             T c_own[P];
@@ -556,16 +787,31 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
                     } else {
                         c_own[m] = 0;
                     }
+                    if constexpr (DA) {
+                        if (j > lane) {  // not moved yet: its current position counts
+                            const double qq = (double)po.w * (double)qi;
+                            if (qq != 0.0) {
+                                da_hist_add(sh, cd, lane, 0, qq < 0.0, d2_exact(xi, yi, zi, po.x, po.y, po.z));
+                                da_hist_add(sh, cd, lane, 1, qq < 0.0, d2_exact(txi, tyi, tzi, po.x, po.y, po.z));
+                            }
+                        } else if (j < lane) {  // decision pending: conflict rule
+                            const double rc2 = cd.da_rc * cd.da_rc;
+                            conf |= d2_exact(xi, yi, zi, po.x, po.y, po.z) < rc2 ||
+                                    d2_exact(xi, yi, zi, pt.x, pt.y, pt.z) < rc2 ||
+                                    d2_exact(txi, tyi, tzi, po.x, po.y, po.z) < rc2 ||
+                                    d2_exact(txi, tyi, tzi, pt.x, pt.y, pt.z) < rc2;
+                        }
+                    }
                 }
                 S += (double)sf;
                 wave_lds_sync();
             }
 
             // ---- band groups g-1..g-band: both outcomes, evaluated ahead of their decisions
-            T c_band[kMaxBand][P];
-            SB ovo_band[kMaxBand], ovt_band[kMaxBand];
+            T c_band[KB][P];
+            SB ovo_band[KB], ovt_band[KB];
 #pragma unroll
-            for (int kb = 0; kb < kMaxBand; ++kb) {
+            for (int kb = 0; kb < KB; ++kb) {
                 ovo_band[kb] = 0;
                 ovt_band[kb] = 0;
 #pragma unroll
@@ -604,6 +850,23 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
                         c_band[kb][m] = tt - o;
                         ovo_band[kb] |= (SB)((SB)(d2ot < s_ij * s_ij) << m);
                         ovt_band[kb] |= (SB)((SB)(d2tt < s_ij * s_ij) << m);
+                        if constexpr (DA) {
+                            if (gp >= 0) {  // decision pending: conflict rule
+                                const double rc2 = cd.da_rc * cd.da_rc;
+                                conf |= d2_exact(xi, yi, zi, po.x, po.y, po.z) < rc2 ||
+                                        d2_exact(xi, yi, zi, pt.x, pt.y, pt.z) < rc2 ||
+                                        d2_exact(txi, tyi, tzi, po.x, po.y, po.z) < rc2 ||
+                                        d2_exact(txi, tyi, tzi, pt.x, pt.y, pt.z) < rc2;
+                            } else {
+                                // before the chain's first group: nothing moved, the
+                                // ion sits at its starting position, which counts
+                                const double qq = (double)po.w * (double)qi;
+                                if (qq != 0.0) {
+                                    da_hist_add(sh, cd, lane, 0, qq < 0.0, d2_exact(xi, yi, zi, po.x, po.y, po.z));
+                                    da_hist_add(sh, cd, lane, 1, qq < 0.0, d2_exact(txi, tyi, tzi, po.x, po.y, po.z));
+                                }
+                            }
+                        }
                     }
                     S += (double)sf;
                     wave_lds_sync();
@@ -623,6 +886,9 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
                 // uniform diameters: overlap with any of these partners iff the
                 // smallest trial distance is below the contact distance
                 T d2t_min = (T)3.0e38;
+                // a working-precision squared distance below this bound may be
+                // below rc^2 exactly (the bound is a relative 1e-5 above it)
+                const T rc2_wide = (T)(cd.da_rc * cd.da_rc * (1.0 + 1e-5));
                 for (int64_t gp = g - nb + 1; gp <= g_last; ++gp) {
                     const int j = bp * kGroup + jl;
                     typename IO::Rec cur;
@@ -649,6 +915,7 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
                         }
                     }
                     T sf = 0;
+                    uint32_t nearm = 0;  // delayed acceptance: partners possibly within rc
 #pragma unroll
                     for (int m = 0; m < P; ++m) {
                         const T4 p = sh.st_old[wave][m];
@@ -661,6 +928,22 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
                             d2t_min = Prec<T>::min(d2t, d2t_min);
                         else
                             ov |= d2t < s_ij * s_ij;
+                        if constexpr (DA) nearm |= (uint32_t)(Prec<T>::min(d2, d2t) < rc2_wide) << m;
+                    }
+                    if constexpr (DA) {
+                        // rare: bin the near partners with exact double distances
+                        if (__ballot(nearm != 0u) != 0ull) {
+                            while (nearm) {
+                                const int m = __builtin_ctz(nearm);
+                                nearm &= nearm - 1u;
+                                const T4 p = sh.st_old[wave][m];
+                                const double qq = (double)p.w * (double)qi;
+                                if (qq != 0.0) {
+                                    da_hist_add(sh, cd, lane, 0, qq < 0.0, d2_exact(xi, yi, zi, p.x, p.y, p.z));
+                                    da_hist_add(sh, cd, lane, 1, qq < 0.0, d2_exact(txi, tyi, tzi, p.x, p.y, p.z));
+                                }
+                            }
+                        }
                     }
                     S += (double)sf;
                     wave_lds_sync();
@@ -673,6 +956,11 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
 
             // ---- hand off to the chain wave once it has released the previous target
             wait_lds_at_least(&sh.consumed, t, ctl);
+            if constexpr (DA) {
+                const uint64_t cb = __ballot(conf);
+                if (lane == 0) sh.part_conf[wave] = cb;
+                da_network<T, M>(sh, cd, wave, lane, da_on, s * (int64_t)cd.n + ion, ion < cd.n);
+            }
             sh.part_s[wave][lane] = S;
             {
                 const uint64_t ob = __ballot(ov);
@@ -681,7 +969,7 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
             sh.ovo_own[wave][lane] = ovo_own;
             sh.ovt_own[wave][lane] = ovt_own;
 #pragma unroll
-            for (int kb = 0; kb < kMaxBand; ++kb) {
+            for (int kb = 0; kb < KB; ++kb) {
                 sh.ovo_b[kb][wave][lane] = ovo_band[kb];
                 sh.ovt_b[kb][wave][lane] = ovt_band[kb];
             }
@@ -691,7 +979,7 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
 #pragma unroll
                 for (int m = 0; m < P; ++m) {
 #pragma unroll
-                    for (int kb = 0; kb < kMaxBand; ++kb) {
+                    for (int kb = 0; kb < KB; ++kb) {
                         cp += c_band[kb][m] > 0 ? c_band[kb][m] : (T)0;
                         cn += c_band[kb][m] < 0 ? c_band[kb][m] : (T)0;
                     }
@@ -705,7 +993,7 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
             for (int m = 0; m < P; ++m) {
                 sh.c_own[lane][wave * P + m] = c_own[m];
 #pragma unroll
-                for (int kb = 0; kb < kMaxBand; ++kb)
+                for (int kb = 0; kb < KB; ++kb)
                     if (kb < band) sh.c_b[kb][lane][wave * P + m] = c_band[kb][m];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -714,20 +1002,27 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
 
             // ---- wave 0 finishes the group: decisions and publication
             if (wave == 0) {
-                chain_step<T, M>(sh, cd, pos_r, rec_r, charge, g_begin, g, t, xi, yi, zi, txi, tyi, tzi,
-                                 wd.w, ctl, c_moves, c_acc, c_wall, c_ov, c_iters, c_early);
+                chain_step<T, M, DA>(sh, cd, pos_r, rec_r, charge, g_begin, g, t, xi, yi, zi, txi, tyi, tzi,
+                                     wd.w, da_on, ctl, ctr);
                 if (g == g_end - 1 && lane == 0) cd.clk[1] = wall_clock64();
             }
         }
     }
-    if (wave == 0 && lane == 0 && c_moves) {
-        atomicAdd(&cd.stats[0], c_moves);
-        atomicAdd(&cd.stats[1], c_acc);
-        atomicAdd(&cd.stats[2], c_wall);
-        atomicAdd(&cd.stats[3], c_ov);
-        atomicAdd(&cd.stats[4], c_moves - c_acc - c_wall - c_ov);
-        atomicAdd(&cd.stats[5], c_iters);
-        atomicAdd(&cd.stats[6], c_early);
+    if (wave == 0 && lane == 0 && ctr.moves) {
+        atomicAdd(&cd.stats[0], ctr.moves);
+        atomicAdd(&cd.stats[1], ctr.acc);
+        atomicAdd(&cd.stats[2], ctr.wall);
+        atomicAdd(&cd.stats[3], ctr.ov);
+        atomicAdd(&cd.stats[4], ctr.moves - ctr.acc - ctr.wall - ctr.ov);
+        atomicAdd(&cd.stats[5], ctr.iters);
+        atomicAdd(&cd.stats[6], ctr.early);
+        if constexpr (DA) {
+            atomicAdd(&cd.stats[7], ctr.da_moves);
+            atomicAdd(&cd.stats[8], ctr.conflicts);
+            atomicAdd(&cd.stats[9], ctr.s1_rej);
+            atomicAdd(&cd.stats[10], ctr.s1_pass);
+            atomicAdd(&cd.stats[11], ctr.s2_rej);
+        }
     }
 }
 
@@ -752,6 +1047,24 @@ energy_scan_kernel(const ChainDesc* __restrict__ chains, int32_t n_sweeps, int64
             if (s0 + s < cd.e_capacity) cd.e_series[s0 + s] = e;
         }
         *cd.e_state = e;
+        // delayed-acceptance drift monitor: at the end of each window, the
+        // stage-2 rejection rate of stage-1 passes against its training-time
+        // value; above ref_rate + delta the chain falls back to the plain
+        // test for good (from the next launch, i.e. the next window)
+        DAState* da = cd.da;
+        const int64_t s_end = s0 + n_sweeps;
+        if (da != nullptr && da->window > 0 && s_end % da->window == 0) {
+            const unsigned long long pass = cd.stats[10], rej = cd.stats[11];
+            const unsigned long long dp = pass - da->win_pass0, dr = rej - da->win_rej0;
+            if (dp > 0) da->last_rate = (double)dr / (double)dp;
+            if (da->active && da->ref_rate >= 0.0 && (int64_t)dp >= da->min_count &&
+                da->last_rate > da->ref_rate + da->delta) {
+                da->active = 0;
+                da->fallback_sweep = s_end;
+            }
+            da->win_pass0 = pass;
+            da->win_rej0 = rej;
+        }
     }
 }
 

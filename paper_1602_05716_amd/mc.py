@@ -38,7 +38,9 @@ class Options(ctypes.Structure):
                 ("chain_id", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p),
                 ("band", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("workgroups", ctypes.c_int32), ("trace_moves", ctypes.c_int64),
-                ("wait_timeout_s", ctypes.c_double), ("record_timing", ctypes.c_int32)]
+                ("wait_timeout_s", ctypes.c_double), ("record_timing", ctypes.c_int32),
+                ("da_rcut", ctypes.c_double), ("da_window", ctypes.c_int32), ("da_delta", ctypes.c_double),
+                ("log_moves", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -49,10 +51,13 @@ class Stats(ctypes.Structure):
                 ("resums", ctypes.c_int64), ("last_drift", ctypes.c_double),
                 ("max_abs_drift", ctypes.c_double), ("band", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("workgroups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("da_active", ctypes.c_int32), ("da_moves", ctypes.c_int64), ("da_conflicts", ctypes.c_int64),
+                ("da_stage1_rejected", ctypes.c_int64), ("da_stage1_passed", ctypes.c_int64),
+                ("da_stage2_rejected", ctypes.c_int64), ("da_fallback_sweep", ctypes.c_int64),
+                ("da_last_rate", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ChainSpec(ctypes.Structure):
@@ -71,7 +76,9 @@ SYMBOLS = ["mc_options_init", "mc_create", "mc_sweep", "mc_energy", "mc_rdf", "m
            "mc_create_batch", "mc_chain_count", "mc_chain_energy", "mc_chain_rdf", "mc_chain_species",
            "mc_chain_positions", "mc_chain_trace", "mc_chain_energy_series", "mc_chain_stats",
            "mc_chain_set_max_disp", "mc_get_schedule", "mc_set_schedule", "mc_chain_launch_ms",
-           "mc_autotune", "mc_destroy", "mc_last_error"]
+           "mc_autotune", "mc_set_surrogate", "mc_get_log", "mc_destroy", "mc_last_error"]
+
+DA_NPARAM = 33153
 
 _f64p = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -117,6 +124,8 @@ def load(path: str = LIB_PATH):
         "mc_set_schedule": ([_hp, _i32p], ctypes.c_int),
         "mc_chain_launch_ms": ([_hp, _f64p], ctypes.c_int),
         "mc_autotune": ([_hp, ctypes.c_int32, ctypes.c_uint64, _f64p], ctypes.c_int),
+        "mc_set_surrogate": ([_hp, ctypes.c_int32, _f64p, ctypes.c_double, ctypes.c_int32], ctypes.c_int),
+        "mc_get_log": ([_hp, ctypes.c_int32, ctypes.c_int64, _u8p, _f64p, _f64p, _u8p], ctypes.c_int),
         "mc_destroy": ([_hp], None),
         "mc_last_error": ([_hp], ctypes.c_char_p),
     }
@@ -411,3 +420,28 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+def _set_surrogate(self, params, ref_stage2_reject=-1.0, active=True, chain=-1):
+    p = np.ascontiguousarray(params, np.float64)
+    if p.size != DA_NPARAM:
+        raise ValueError("expected %d network parameters" % DA_NPARAM)
+    self._check(self._L.mc_set_surrogate(self.h, int(chain), _p(p, _f64p), float(ref_stage2_reject),
+                                         1 if active else 0))
+
+
+def _get_log(self, n, chain=0):
+    """Logged moves: dict of feats [n, 256] uint8, dE, dEh, flags."""
+    f = np.zeros((n, 256), np.uint8)
+    de = np.zeros(n)
+    deh = np.zeros(n)
+    fl = np.zeros(n, np.uint8)
+    self._check(self._L.mc_get_log(self.h, int(chain), int(n), _p(f, _u8p), _p(de, _f64p), _p(deh, _f64p),
+                                   _p(fl, _u8p)))
+    return {"feats": f, "dE": de, "dEh": deh, "flags": fl}
+
+
+Chain.set_surrogate = _set_surrogate
+Chain.get_log = _get_log
+Batch.set_surrogate = _set_surrogate
+Batch.get_log = _get_log

@@ -1,0 +1,149 @@
+"""Delayed acceptance on the GPU against the oracle's two-stage chain (C ABI).
+
+The two-stage rule (Christen and Fox 2005; not in the paper) keeps the
+paper's exact dE (Sec. 2, Eq. Delta E_ij) as its second stage.  Checked here,
+move by move along the GPU's own trajectory: the neighbour histograms (exact
+integers), the conflict rule (exact), the surrogate dEh (float sums against
+double), the exact dE, and every decision -- the GPU's decision must be the
+oracle's except within rounding of a threshold.  Also: logging in the plain
+mode and the drift monitor's fall-back.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _sys(n, phi, lB, seed):
+    from paper_1602_05716_amd import inputs
+    sy = inputs.electrolyte(n // 2, n - n // 2, 1.0, -1.0, 1.0, 1.0, phi, lB)
+    sy.xyz = inputs.random_start(sy, seed)
+    return sy
+
+
+def _params(seed, scale):
+    from oracle import oracle as O
+    rng = np.random.default_rng(seed)
+    return O.bf16(rng.normal(0.0, scale, O.da_nparam()))
+
+
+def _feat_ints(f8):
+    return f8.astype(np.int32)
+
+
+def _check_da(oracle, sy, precision, sweeps, seed, D, params, da_on=True, tol_de=None, rc=4.0):
+    from paper_1602_05716_amd import mc
+    n_moves = sweeps * sy.n
+    _say("da %s N=%d sweeps=%d seed=%d da_on=%s rc=%g" % (precision, sy.n, sweeps, seed, da_on, rc))
+    with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision=precision, max_disp=0.5 * D,
+                  trace_moves=n_moves, log_moves=n_moves, resum_every=0, waves=4, da_rcut=rc) as ch:
+        if da_on:
+            ch.set_surrogate(params, -1.0, True)
+        ch.sweep(sweeps, seed)
+        acc, de = ch.trace(n_moves)
+        lg = ch.get_log(n_moves)
+        x = ch.positions()
+        st = ch.stats()
+    f32 = precision == "fp32"
+    x0 = sy.xyz.astype(np.float32).astype(np.float64) if f32 else sy.xyz
+    r = oracle.da_run(x0, sy.q, sy.sigma, sy.R, sy.lB, D, seed, 0, 0, n_moves, params, rc=rc,
+                      band=st["band"], da_on=1 if da_on else 0, f32=f32, acc_given=acc, features=True)
+    # the trajectory is fixed by the decisions and the trial formula
+    assert np.array_equal(x, r["x"])
+    assert np.all(lg["flags"] & 0x80)
+    conflict = (lg["flags"] >> 2) & 1
+    assert np.array_equal(conflict, (r["flags"] >> 2) & 1), "conflict rule differs"
+    nc = conflict == 0
+    assert np.array_equal(_feat_ints(lg["feats"][nc]), r["features"][nc]), "histograms differ"
+    # exact dE
+    if tol_de is None:
+        err = np.abs(de - r["dE"]) / np.maximum(np.abs(r["dE"]), 1.0)
+        assert err.max() < 1e-10, err.max()
+    else:
+        err = np.abs(de - r["dE"]) / np.maximum(np.abs(r["dE"]), 1.0)
+        assert err.max() <= tol_de, err.max()
+    assert np.allclose(lg["dE"], de, rtol=0, atol=0)
+    # surrogate
+    da_moves = nc if da_on else np.zeros_like(nc)
+    if da_on:
+        # float sums against double; a hidden activation may round to the
+        # neighbouring bfloat16 value on one side (a 2^-8 relative step)
+        d = np.abs(lg["dEh"][da_moves] - r["dEh"][da_moves]) / (1.0 + np.abs(r["dEh"][da_moves]))
+        assert d.max() <= 2e-3, d.max()
+    # decisions: equal to the oracle's own, except within rounding of a threshold
+    dis = np.flatnonzero(acc != r["own"])
+    thr3 = -np.log(np.maximum(r["u3"], 1e-300))
+    thr2 = -np.log(np.maximum(r["u2"], 1e-300))
+    band_tol = 1e-6 if tol_de is None else 2 * TOL32
+    for k in dis:
+        fl = int(r["flags"][k])
+        near = abs(r["dE"][k] - thr3[k]) <= band_tol * max(1.0, abs(r["dE"][k]))
+        if da_on and not conflict[k]:
+            near = (abs(r["dEh"][k] - thr3[k]) <= 1e-3 * (1.0 + abs(thr3[k])) or
+                    abs(r["dE"][k] - r["dEh"][k] - thr2[k]) <= 1e-3 * (1.0 + abs(thr2[k])))
+        assert near or (fl & 3), ("decision differs away from a threshold", int(k), fl)
+    assert dis.size <= max(2, n_moves // 2000)
+    return st, r, lg
+
+
+def test_da_fp64_two_stage_parity(oracle):
+    """Double path, random network (stage 1 rejects a fair share), band 1.
+    With 64-ion groups a move has a conflict when one of the ~96 ions with a
+    pending decision is near; rc = 2 at N = 2048 leaves about half the moves
+    to the two-stage test."""
+    sy = _sys(2048, 0.05, 0.8, seed=41)
+    p = _params(7, 0.2)
+    st, r, lg = _check_da(oracle, sy, "fp64", 2, 0xDA64, 2.0, p, rc=2.0)
+    assert st["band"] == 1 and st["da_active"] == 1
+    n_moves = 2 * sy.n
+    assert st["da_moves"] + st["da_conflicts"] == n_moves and st["da_moves"] > n_moves // 4
+    s1 = ((lg["flags"] >> 3) & 1).sum()
+    assert st["da_stage1_rejected"] == s1 and s1 > 200
+
+
+def test_da_fp32_two_stage_parity(oracle):
+    """Float path, larger moves, rc = 2.5."""
+    sy = _sys(4096, 0.05, 0.7, seed=42)
+    p = _params(8, 0.2)
+    st, r, lg = _check_da(oracle, sy, "fp32", 1, 0xDA32, 3.0, p, tol_de=TOL32, rc=2.5)
+    assert st["da_active"] == 1 and st["da_stage1_rejected"] > 200
+
+
+def test_plain_mode_logging_matches_oracle(oracle):
+    """Logging without a surrogate: plain decisions (bit-exact in double),
+    exact histograms and conflict flags for every logged move."""
+    sy = _sys(200, 0.08, 0.7, seed=43)
+    p = np.zeros(oracle.da_nparam())
+    st, r, lg = _check_da(oracle, sy, "fp64", 3, 0x106, 1.5, p, da_on=False)
+    assert st["da_active"] == 0 and np.all(lg["dEh"] == 0.0)
+
+
+def test_drift_monitor_falls_back(oracle):
+    """A reference rate of 0 with delta 0: the first window with a stage-2
+    rejection switches the chain to the plain test from the next window on;
+    the moves before and after follow the oracle's DA and plain chains."""
+    from paper_1602_05716_amd import mc
+    sy = _sys(1024, 0.05, 0.8, seed=44)
+    p = _params(9, 0.2)
+    D, seed, sweeps = 2.0, 0xFA11, 4
+    n_moves = sweeps * sy.n
+    with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision="fp64", max_disp=0.5 * D,
+                  trace_moves=n_moves, resum_every=0, waves=4, da_window=2, da_delta=0.0, da_rcut=1.5) as ch:
+        ch.set_surrogate(p, 0.0, True)
+        ch.sweep(sweeps, seed)
+        acc, de = ch.trace(n_moves)
+        st = ch.stats()
+    assert st["da_active"] == 0 and st["da_fallback_sweep"] == 2, st
+    w = 2 * sy.n
+    r1 = oracle.da_run(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, D, seed, 0, 0, w, p, rc=1.5, band=1, da_on=1,
+                       acc_given=acc[:w])
+    assert r1["mismatches"] <= 2
+    r2 = oracle.da_run(r1["x"], sy.q, sy.sigma, sy.R, sy.lB, D, seed, 0, 2, n_moves - w, p, rc=1.5, band=1,
+                       da_on=0, acc_given=acc[w:])
+    assert r2["mismatches"] == 0
