@@ -187,6 +187,90 @@ def batched_leg(args, log_fn=None):
             "batched_over_sequential": t_seq / t_batch}
 
 
+def _gr_sample_run(chain, sweeps, seed, every):
+    """Runs `sweeps` sweeps with a g(r) sample every `every` sweeps; returns
+    (wall seconds, energy series, g(r) of the first and second halves)."""
+    import torch
+    s0 = chain.stats()["sweeps"]
+    chain.rdf_reset()
+    halves = []
+    t = 0.0
+    for half in range(2):
+        for _ in range(sweeps // 2 // every):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            chain.sweep(every, seed)
+            chain.rdf_sample()
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+        halves.append(chain.rdf())
+        chain.rdf_reset()
+    e = chain.energy_series(chain.stats()["sweeps"])[s0:]
+    return t, e, halves
+
+
+def da_leg(args, md):
+    """Surrogate delayed acceptance on the N=32768 system: log moves of a
+    plain run, train the network on the GPU, then run the two-stage chain and
+    the plain chain from the same state for the same number of sweeps."""
+    import torch
+    from paper_1602_05716_amd import analysis, inputs, mc
+    system = inputs.large_fp32()
+    n = system.n
+    stream = torch.cuda.Stream()
+    sweeps_log = max(1, -(-args.da_log_moves // n))
+    n_log = sweeps_log * n
+    seed = 0x5EED0005
+    with mc.Chain(system.xyz, system.q, system.sigma, system.R, system.lB, precision="fp32", max_disp=md,
+                  resum_every=100, waves=4, log_moves=n_log, hip_stream=stream.cuda_stream) as lg_chain:
+        lg_chain.sweep(sweeps_log, seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = lg_chain.train_surrogate(n_log, epochs=args.da_epochs, batch=4096, lr=2e-3, seed=7)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        x0 = lg_chain.positions()
+    out = {"workload": "1:1 N=32768 phi=0.05 l_B=0.7 (the plain benchmark's system), %d logged moves, "
+                       "network 128-128-128-1 bfloat16" % n_log,
+           "train_s": t_train, "train_loss": [float(v) for v in tr["loss"]], "val_loss": tr["val_loss"],
+           "ref_stage2_reject": tr["ref_stage2_reject"], "sweeps": args.da_sweeps}
+    runs = {}
+    for mode in ("plain", "da"):
+        kw = dict(precision="fp32", max_disp=md, resum_every=100, hip_stream=stream.cuda_stream, rdf_bins=200,
+                  rdf_rmax=10.0)
+        if mode == "da":
+            kw["waves"] = 4
+        with mc.Chain(x0, system.q, system.sigma, system.R, system.lB, **kw) as c:
+            if mode == "da":
+                c.set_surrogate(tr["params"], tr["ref_stage2_reject"], True)
+            c.sweep(2, seed + 1)  # first launch out of the timed region
+            t, e, halves = _gr_sample_run(c, args.da_sweeps, seed + 2, 10)
+            st = c.stats()
+            ess = analysis.effective_samples(e)
+            g = 0.5 * (halves[0]["g"] + halves[1]["g"])
+            runs[mode] = {"wall_s": t, "ess": ess, "ess_per_s": ess / t, "moves_per_s": args.da_sweeps * n / t,
+                          "acceptance": st["accepted"] / max(1, st["moves"]), "g": g, "halves": halves,
+                          "stats": st}
+    # g(r) accuracy: RMS difference between the two runs against the plain
+    # run's own half-to-half RMS difference (the statistical noise scale)
+    r = (np.arange(200) + 0.5) * 0.05
+    sel = r >= 1.0
+    def rms(a, b):
+        return float(np.sqrt(np.mean((a[..., sel] - b[..., sel]) ** 2)))
+    ph = runs["plain"]["halves"]
+    out["plain"] = {k: v for k, v in runs["plain"].items() if k in ("wall_s", "ess", "ess_per_s", "moves_per_s", "acceptance")}
+    out["da"] = {k: v for k, v in runs["da"].items() if k in ("wall_s", "ess", "ess_per_s", "moves_per_s", "acceptance")}
+    sd = runs["da"]["stats"]
+    out["da"].update({"stage1_rejected": sd["da_stage1_rejected"], "stage1_passed": sd["da_stage1_passed"],
+                      "stage2_rejected": sd["da_stage2_rejected"], "conflict_moves": sd["da_conflicts"],
+                      "two_stage_moves": sd["da_moves"], "fallback_sweep": sd["da_fallback_sweep"],
+                      "active_at_end": sd["da_active"]})
+    out["g_rms_da_vs_plain"] = rms(runs["da"]["g"], runs["plain"]["g"])
+    out["g_rms_plain_half_vs_half"] = rms(ph[0]["g"], ph[1]["g"])
+    out["ess_per_s_da_over_plain"] = out["da"]["ess_per_s"] / out["plain"]["ess_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +286,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--batch-sweeps", type=int, default=1000)
     ap.add_argument("--seq-sweeps", type=int, default=20)
+    ap.add_argument("--no-da", action="store_true", help="skip the surrogate delayed-acceptance leg")
+    ap.add_argument("--da-log-moves", type=int, default=1000000)
+    ap.add_argument("--da-epochs", type=int, default=6)
+    ap.add_argument("--da-sweeps", type=int, default=400)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -272,6 +360,11 @@ def main():
         log("batched ensemble leg")
         batched = batched_leg(args)
 
+    da = None
+    if not args.no_da:
+        log("surrogate delayed-acceptance leg")
+        da = da_leg(args, md)
+
     cpu = None
     if not args.no_cpu:
         log("timing the CPU oracle (%d sweep(s))" % args.cpu_sweeps)
@@ -294,8 +387,10 @@ def main():
         "ess_per_s": {"plain": ess / elapsed,
                       "batched": batched["ess_per_s"] if batched else None,
                       "batched_one_after_another": batched["one_after_another"]["ess_per_s"] if batched else None,
-                      "surrogate_da": None},
+                      "surrogate_da": da["da"]["ess_per_s"] if da else None,
+                      "plain_same_run_as_da": da["plain"]["ess_per_s"] if da else None},
         "batched": batched,
+        "surrogate_da": da,
         "energy": {"tau_int_sweeps": tau, "e_running": e_run, "e_resum": e_exact,
                    "max_abs_drift_per_resum": st1["max_abs_drift"]},
         "roofline": roofline,

@@ -363,6 +363,35 @@ int mc_set_surrogate(mc_handle* h, int32_t chain, const double* params, double r
 int mc_get_log(mc_handle* h, int32_t chain, int64_t n, uint8_t* feats, double* dE, double* dEh,
                uint8_t* flags);
 
+/*
+ * One forward and backward pass of the network on the GPU (bfloat16 matrix
+ * products with float sums), for checks: feats [batch*256] byte histograms
+ * of batch moves (as from mc_get_log), target [batch] the values eps(new) -
+ * eps(old) should take, params [MC_DA_NPARAM] (used at bfloat16 precision).
+ * *loss = mean((eps(new) - eps(old) - target)^2); grad [MC_DA_NPARAM] its
+ * gradient (nullable outputs).  batch a positive multiple of 32.  Uses the
+ * current HIP device and its default stream; needs no handle.
+ */
+int mc_mlp_grad(int32_t batch, const uint8_t* feats, const double* target, const double* params,
+                double* loss, double* grad);
+
+/*
+ * Trains the network on the GPU on chain `chain`'s log: the first n_moves
+ * logged moves without a conflict, wall or overlap rejection; the last tenth
+ * of them held out.  Target of a move: dE / l_B; loss: mean squared error of
+ * eps(phi(x~_i)) - eps(phi(x_i)).  Adam (beta 0.9, 0.999) with learning rate
+ * lr on float master weights, minibatches of `batch` moves (a multiple of 32)
+ * drawn in an order fixed by seed, `epochs` passes.  params_in (nullable)
+ * starts the training, else He-initialised weights from seed.  Outputs:
+ * params_out [MC_DA_NPARAM] (bfloat16 values), loss_out [epochs] (nullable)
+ * the mean training loss of each epoch, *val_loss (nullable) the held-out
+ * loss, *ref_stage2_reject (nullable) the stage-2 rejection rate the network
+ * gives on the held-out moves (for mc_set_surrogate's drift monitor).
+ */
+int mc_train_surrogate(mc_handle* h, int32_t chain, int64_t n_moves, int32_t epochs, int32_t batch,
+                       double lr, uint64_t seed, const double* params_in, double* params_out,
+                       double* loss_out, double* val_loss, double* ref_stage2_reject);
+
 /* Releases every resource of the handle; NULL is allowed. */
 void mc_destroy(mc_handle* h);
 

@@ -24,6 +24,7 @@
 
 #include "../../include/mc.h"
 #include "mc_aux_kernels.hpp"
+#include "mc_internal.hpp"
 #include "mc_sweep_kernel.hpp"
 
 using namespace mcdev;
@@ -1052,6 +1053,23 @@ int last_launch_ms(mc_handle* h, std::vector<double>& ms) {
 }
 
 }  // namespace
+
+int mc_internal_log(mc_handle* h, int32_t chain, MCLogView* out) {
+    Chain* c = get_chain(h, chain);
+    if (!c || !out) return h ? fail(h, MC_E_ARG, "bad chain index") : MC_E_ARG;
+    if (c->log_cap == 0) return fail(h, MC_E_ARG, "the chain has no move log (log_moves)");
+    int rc = sync_check(h);
+    if (rc) return rc;
+    out->feat = c->log_feat;
+    out->de = c->log_de;
+    out->flags = c->log_flags;
+    out->cap = c->log_cap;
+    out->lB = c->lB;
+    out->stream = h->stream;
+    return MC_OK;
+}
+
+int mc_internal_fail(mc_handle* h, int code, const char* msg) { return fail(h, code, msg); }
 
 extern "C" {
 

@@ -76,7 +76,8 @@ SYMBOLS = ["mc_options_init", "mc_create", "mc_sweep", "mc_energy", "mc_rdf", "m
            "mc_create_batch", "mc_chain_count", "mc_chain_energy", "mc_chain_rdf", "mc_chain_species",
            "mc_chain_positions", "mc_chain_trace", "mc_chain_energy_series", "mc_chain_stats",
            "mc_chain_set_max_disp", "mc_get_schedule", "mc_set_schedule", "mc_chain_launch_ms",
-           "mc_autotune", "mc_set_surrogate", "mc_get_log", "mc_destroy", "mc_last_error"]
+           "mc_autotune", "mc_set_surrogate", "mc_get_log", "mc_mlp_grad", "mc_train_surrogate",
+           "mc_destroy", "mc_last_error"]
 
 DA_NPARAM = 33153
 
@@ -126,6 +127,9 @@ def load(path: str = LIB_PATH):
         "mc_autotune": ([_hp, ctypes.c_int32, ctypes.c_uint64, _f64p], ctypes.c_int),
         "mc_set_surrogate": ([_hp, ctypes.c_int32, _f64p, ctypes.c_double, ctypes.c_int32], ctypes.c_int),
         "mc_get_log": ([_hp, ctypes.c_int32, ctypes.c_int64, _u8p, _f64p, _f64p, _u8p], ctypes.c_int),
+        "mc_mlp_grad": ([ctypes.c_int32, _u8p, _f64p, _f64p, _f64p, _f64p], ctypes.c_int),
+        "mc_train_surrogate": ([_hp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                ctypes.c_uint64, _f64p, _f64p, _f64p, _f64p, _f64p], ctypes.c_int),
         "mc_destroy": ([_hp], None),
         "mc_last_error": ([_hp], ctypes.c_char_p),
     }
@@ -445,3 +449,34 @@ Chain.set_surrogate = _set_surrogate
 Chain.get_log = _get_log
 Batch.set_surrogate = _set_surrogate
 Batch.get_log = _get_log
+
+
+def mlp_grad(feats, target, params):
+    """(loss, grad) of the network on the GPU (mc_mlp_grad)."""
+    f = np.ascontiguousarray(feats, np.uint8).reshape(-1, 256)
+    t = np.ascontiguousarray(target, np.float64)
+    p = np.ascontiguousarray(params, np.float64)
+    loss = ctypes.c_double()
+    g = np.zeros(DA_NPARAM)
+    rc = lib().mc_mlp_grad(len(f), _p(f, _u8p), _p(t, _f64p), _p(p, _f64p), ctypes.byref(loss), _p(g, _f64p))
+    if rc != MC_OK:
+        raise MCError(rc, "mc_mlp_grad failed")
+    return loss.value, g
+
+
+def _train_surrogate(self, n_moves, epochs=10, batch=1024, lr=1e-3, seed=1, params_in=None, chain=0):
+    """Trains the surrogate on the chain's log; returns a dict with params,
+    per-epoch losses, held-out loss and the stage-2 rejection reference."""
+    out = np.zeros(DA_NPARAM)
+    losses = np.zeros(epochs)
+    vl = ctypes.c_double()
+    ref = ctypes.c_double()
+    pin = None if params_in is None else np.ascontiguousarray(params_in, np.float64)
+    self._check(self._L.mc_train_surrogate(self.h, int(chain), int(n_moves), int(epochs), int(batch), float(lr),
+                                           int(seed), _p(pin, _f64p) if pin is not None else None, _p(out, _f64p),
+                                           _p(losses, _f64p), ctypes.byref(vl), ctypes.byref(ref)))
+    return {"params": out, "loss": losses, "val_loss": vl.value, "ref_stage2_reject": ref.value}
+
+
+Chain.train_surrogate = _train_surrogate
+Batch.train_surrogate = _train_surrogate
