@@ -47,11 +47,21 @@ def build(verbose: bool = False) -> str:
 
 
 def asm(out_path: str) -> str:
-    """Writes the gfx950 assembly of the device code (for inspection)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [HIPCC] + [f for f in FLAGS if f not in ("-shared", "-fPIC")] + [
-        "--cuda-device-only", "-S", "-I", os.path.join(HERE, "..", "include"), "-o", out_path] + srcs
-    subprocess.check_call(cmd)
+    """Writes the gfx950 assembly of the device code (for inspection), all
+    sources concatenated into out_path."""
+    parts = []
+    for src in SOURCES:
+        part = out_path + "." + src + ".s"
+        cmd = [HIPCC] + [f for f in FLAGS if f not in ("-shared", "-fPIC")] + [
+            "--cuda-device-only", "-S", "-I", os.path.join(HERE, "..", "include"), "-o", part,
+            os.path.join(CSRC, src)]
+        subprocess.check_call(cmd)
+        parts.append(part)
+    with open(out_path, "w") as out:
+        for part in parts:
+            with open(part) as f:
+                out.write(f.read())
+            os.remove(part)
     return out_path
 
 

@@ -130,6 +130,7 @@ struct Chain {
     // delayed acceptance
     DAState* da = nullptr;        // arena
     float* da_w = nullptr;        // [kDaParams], own allocation once installed
+    uint16_t* da_wb = nullptr;    // [2][128 x 128] bfloat16 W1 and W2
     uint32_t* log_feat = nullptr; // [log_cap][64], own allocation
     double* log_de = nullptr;
     double* log_deh = nullptr;
@@ -219,11 +220,12 @@ void drop_events(mc_handle* h) {
 void free_all(mc_handle* h) {
     drop_events(h);
     for (Chain& c : h->chains) {
-        void* own[] = {c.e_series, c.de_group, c.da_w, c.log_feat, c.log_de, c.log_deh, c.log_flags};
+        void* own[] = {c.e_series, c.de_group, c.da_w, c.da_wb, c.log_feat, c.log_de, c.log_deh, c.log_flags};
         for (void* b : own)
             if (b) (void)hipFree(b);
         c.e_series = c.de_group = nullptr;
         c.da_w = nullptr;
+        c.da_wb = nullptr;
         c.log_feat = nullptr;
         c.log_de = c.log_deh = nullptr;
         c.log_flags = nullptr;
@@ -455,6 +457,8 @@ void fill_desc(mc_handle* h) {
         d.rdf_counts = c.rdf_counts;
         d.rdf_centres = c.rdf_centres;
         d.da_w = c.da_w;
+        d.da_w1b = c.da_wb;
+        d.da_w2b = c.da_wb ? c.da_wb + kDaIn * kDaHid : nullptr;
         d.da = c.da;
         d.da_rc = h->opt.da_rcut;
         d.da_dr = h->opt.da_rcut / (double)kDaBins;
@@ -1358,6 +1362,7 @@ int mc_set_surrogate(mc_handle* h, int32_t chain, const double* params, double r
     if (h->waves != 4) return fail(h, MC_E_ARG, "delayed acceptance needs 4 waves per workgroup");
     if (!is_finite(ref_stage2_reject)) return fail(h, MC_E_ARG, "ref_stage2_reject must be finite");
     std::vector<float> w(kDaParams);
+    std::vector<uint16_t> wb(2 * kDaIn * kDaHid);
     for (int k = 0; k < kDaParams; ++k) {
         if (!is_finite(params[k])) return fail(h, MC_E_ARG, "non-finite network parameter");
         float f = (float)params[k];
@@ -1367,6 +1372,16 @@ int mc_set_surrogate(mc_handle* h, int32_t chain, const double* params, double r
         b &= 0xFFFF0000u;
         std::memcpy(&f, &b, 4);
         w[k] = f;
+        // bfloat16 copies of the two hidden layers' matrices, transposed
+        // ([hidden unit][input]) for the kernel's 8-byte operand loads
+        const int oW2 = kDaIn * kDaHid + kDaHid;
+        if (k < kDaIn * kDaHid) {
+            const int in = k / kDaHid, hu = k % kDaHid;
+            wb[hu * kDaIn + in] = (uint16_t)(b >> 16);
+        } else if (k >= oW2 && k < oW2 + kDaHid * kDaHid) {
+            const int in = (k - oW2) / kDaHid, hu = (k - oW2) % kDaHid;
+            wb[kDaIn * kDaHid + hu * kDaHid + in] = (uint16_t)(b >> 16);
+        }
     }
     int rc = sync_check(h);
     if (rc) return rc;
@@ -1374,7 +1389,9 @@ int mc_set_surrogate(mc_handle* h, int32_t chain, const double* params, double r
         if (chain >= 0 && k != chain) continue;
         Chain& c = h->chains[k];
         if (!c.da_w && (rc = dalloc(h, &c.da_w, sizeof(float) * kDaParams))) return rc;
+        if (!c.da_wb && (rc = dalloc(h, &c.da_wb, sizeof(uint16_t) * wb.size()))) return rc;
         HIPCHECK(h, hipMemcpy(c.da_w, w.data(), sizeof(float) * kDaParams, hipMemcpyHostToDevice));
+        HIPCHECK(h, hipMemcpy(c.da_wb, wb.data(), sizeof(uint16_t) * wb.size(), hipMemcpyHostToDevice));
         unsigned long long st[ST_N];
         HIPCHECK(h, hipMemcpy(st, c.stats, sizeof(st), hipMemcpyDeviceToHost));
         DAState ds;

@@ -102,6 +102,8 @@ struct ChainDesc {
     unsigned long long* rdf_centres;  // [ntypes]
     // delayed acceptance (kernels with DA = true only)
     const float* da_w;   // [kDaParams] network parameters (bfloat16 values held in float)
+    const uint16_t* da_w1b;  // [128 x 128] W1 as bfloat16, transposed (row = hidden unit)
+    const uint16_t* da_w2b;  // [128 x 128] W2 as bfloat16, transposed
     DAState* da;         // monitor state
     double da_rc;        // histogram range
     double da_dr;        // histogram bin width da_rc / 64
@@ -239,6 +241,11 @@ struct SweepShared {
     uint64_t part_conf[DA ? M : 1];
     double deh[DA ? kGroup : 1];
     float part_out[DA ? M : 1][2][DA ? kGroup : 1];
+    // the network's two matrices, transposed ([hidden unit][input]), as
+    // bfloat16, rows padded to 132 values (8-byte reads free of bank
+    // conflicts); loaded once per launch
+    static constexpr bool kWtsLds = DA && sizeof(T) == 4;  // (the double kernel reads them from memory)
+    uint16_t wts[kWtsLds ? 2 * kDaHid : 1][kWtsLds ? kDaIn + 4 : 1];
     // bfloat16 hidden activations [mover][position][unit] of the network, in
     // the space of c_own and c_b (free between the chain wave's release and
     // the next hand-off)
@@ -501,8 +508,8 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
 
     __builtin_amdgcn_s_setprio(0);
 #ifdef MC_TIMELINE
-    if (lane == 0 && 4 * (g + 1) <= cd.trace_cap) {
-        uint64_t* tl = (uint64_t*)cd.trace_de + 4 * g;
+    if (lane == 0 && 8 * (g + 1) <= cd.trace_cap) {
+        uint64_t* tl = (uint64_t*)cd.trace_de + 8 * g;
         tl[0] = tl0;
         tl[1] = tl1;
         tl[2] = tl2;
@@ -581,104 +588,165 @@ __device__ __forceinline__ float bf16_round(float v) {
     return __builtin_bit_cast(float, b & 0xFFFF0000u);
 }
 
-// Delayed-acceptance stage of one target group, run by all M waves between
+// Delayed-acceptance stage of one target group, run by all 4 waves between
 // the chain wave's release of the hand-off buffer and the next hand-off:
 // logs the movers' histograms, evaluates the network eps at both positions
-// of every mover (wave w computes hidden units [w U, (w + 1) U) of both
-// layers; sums in float, bfloat16 activations), leaves
-// dEh = l_B (eps(trial) - eps(old)) in sh.deh and clears the histograms.
+// of every mover and leaves dEh = l_B (eps(trial) - eps(old)) in sh.deh, then
+// clears the histograms.  Both hidden layers run on the matrix cores as
+// [128 rows x 128] x [128 x 128] bfloat16 products with float sums
+// (v_mfma_f32_32x32x8bf16_1k): row r = 64 * position + mover, wave w takes
+// rows 32 w .. 32 w + 31 and all four 32-column tiles (the matrices are
+// read from LDS, where the kernel put them at its start); lane l holds
+// A[l % 32][4 (l / 32) + v], B[4 (l / 32) + v][l % 32] and
+// D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].  Hidden activations are
+// rounded to bfloat16.
+typedef short da_bf16x4 __attribute__((ext_vector_type(4)));
+typedef float da_f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ short bf16_bits(float v) {
+    return (short)(__builtin_bit_cast(uint32_t, bf16_round(v)) >> 16);
+}
+
 template <typename T, int M>
 __device__ __forceinline__ void da_network(SweepShared<T, M, true>& sh, const ChainDesc& cd, int wave, int lane,
-                                           bool da_on, int64_t mv, bool valid) {
-    constexpr int U = kDaHid / M;     // hidden units per wave
+                                           bool da_on, int64_t mv, bool valid, int64_t g) {
+#ifdef MC_TIMELINE
+    // diagnostic build only: stamps of the network phase after the chain stamps
+    uint64_t* tln = (uint64_t*)cd.trace_de + 8 * g + 4;
+    const bool stamp = wave == 0 && lane == 0 && 8 * (g + 1) <= cd.trace_cap;
+    if (stamp) tln[0] = wall_clock64();
+#else
+    (void)g;
+#endif
+    static_assert(M == 4, "the network phase assumes 4 waves");
     constexpr int WW = 64 / M;        // histogram words logged and cleared per wave
     constexpr int H1S = 2 * kDaHid + 2;  // row stride in bfloat16 values (odd word stride)
     static_assert(sizeof(sh.c_own) + sizeof(sh.c_b) >= sizeof(uint16_t) * kGroup * H1S,
                   "hidden activations must fit in the candidate space");
     __syncthreads();  // every histogram add of this target is done
+#ifdef MC_TIMELINE
+    if (stamp) tln[1] = wall_clock64();
+#endif
     if (valid && mv < cd.log_cap) {
         uint32_t* dst = cd.log_feat + mv * 64;
 #pragma unroll
         for (int k = 0; k < WW; ++k) dst[wave * WW + k] = sh.hist[lane][wave * WW + k];
     }
     uint16_t* h1 = sh.h1();
-    const float* W1 = cd.da_w;
-    const float* b1 = W1 + kDaIn * kDaHid;
-    const float* W2 = b1 + kDaHid;
-    const float* b2 = W2 + kDaHid * kDaHid;
-    const float* w3 = b2 + kDaHid;
-    constexpr int UC = 8;  // hidden units per pass (bounded register use)
+    float* outs = &sh.part_out[0][0][0];  // [128] network outputs by row
+    // biases and the last layer are read through a buffer resource: its loads
+    // wait on the vector-memory counter only, so the LDS traffic of this
+    // phase never waits for them (generic-pointer loads count on both)
+    const __amdgpu_buffer_rsrc_t wr = make_rsrc((void*)cd.da_w, (uint32_t)(sizeof(float) * kDaParams));
+    auto wload = [&](int k) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(wr, (uint32_t)(4 * k), 0, 0));
+    };
+    constexpr int oB1 = kDaIn * kDaHid, oB2 = oB1 + kDaHid + kDaHid * kDaHid, oW3 = oB2 + kDaHid;
+    // B fragment (4 consecutive inputs k of hidden unit `unit`) of layer `layer`
+    const __amdgpu_buffer_rsrc_t wbr = make_rsrc((void*)cd.da_w1b, (uint32_t)(4u * kDaIn * kDaHid));
+    auto bfrag = [&](int layer, int unit, int k) -> uint2 {
+        if constexpr (SweepShared<T, M, true>::kWtsLds)
+            return *reinterpret_cast<const uint2*>(&sh.wts[layer * kDaHid + unit][k]);
+        else
+            return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(
+                                                 wbr, (uint32_t)(2 * ((layer * kDaHid + unit) * kDaIn + k)), 0, 0));
+    };
+    // this lane's A row
+    const int arow = wave * 32 + (lane & 31);
+    const int amover = arow & 63, apos = arow >> 6;
+    const int kq = (lane >> 5) * 4;
+    // B fragments of a layer: the transposed bfloat16 matrix gives each lane
+    // its four consecutive k of column 32 t + l % 32 in one 8-byte load; all
+    // 64 loads of a layer are issued before its products
+    const int bcol = lane & 31;
     if (da_on) {
-#pragma unroll 1
-        for (int hc = wave * U; hc < wave * U + U; hc += UC) {
-            float a0[UC], a1[UC];
+        da_f32x16 acc[4];
 #pragma unroll
-            for (int u = 0; u < UC; ++u) a0[u] = a1[u] = b1[hc + u];
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
 #pragma unroll 2
-            for (int kw = 0; kw < kDaIn / 4; ++kw) {
-                const uint32_t f0w = sh.hist[lane][kw], f1w = sh.hist[lane][kDaIn / 4 + kw];
+        for (int j = 0; j < kDaIn / 8; ++j) {
+            const uint32_t w = sh.hist[amover][apos * 32 + (8 * j + kq) / 4];
+            da_bf16x4 a;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const float f0 = (float)((f0w >> (8 * c)) & 0xFFu), f1 = (float)((f1w >> (8 * c)) & 0xFFu);
-                    const float* wr = W1 + (4 * kw + c) * kDaHid + hc;
+            for (int v = 0; v < 4; ++v) a[v] = bf16_bits((float)((w >> (8 * v)) & 0xFFu));
 #pragma unroll
-                    for (int u = 0; u < UC; ++u) {
-                        a0[u] = __builtin_fmaf(f0, wr[u], a0[u]);
-                        a1[u] = __builtin_fmaf(f1, wr[u], a1[u]);
-                    }
-                }
+            for (int t = 0; t < 4; ++t) {
+                const uint2 bv = bfrag(0, 32 * t + bcol, 8 * j + kq);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, __builtin_bit_cast(da_bf16x4, bv), acc[t], 0, 0, 0);
             }
+        }
 #pragma unroll
-            for (int u = 0; u < UC; ++u) {
-                h1[lane * H1S + hc + u] =
-                    (uint16_t)(__builtin_bit_cast(uint32_t, bf16_round(a0[u] > 0.f ? a0[u] : 0.f)) >> 16);
-                h1[lane * H1S + kDaHid + hc + u] =
-                    (uint16_t)(__builtin_bit_cast(uint32_t, bf16_round(a1[u] > 0.f ? a1[u] : 0.f)) >> 16);
+        for (int t = 0; t < 4; ++t) {
+            const int col = 32 * t + (lane & 31);
+            const float bias = wload(oB1 + col);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r = wave * 32 + 8 * (i / 4) + 4 * (lane >> 5) + (i % 4);
+                const float z = acc[t][i] + bias;
+                h1[(r & 63) * H1S + (r >> 6) * kDaHid + col] = (uint16_t)bf16_bits(z > 0.f ? z : 0.f);
             }
         }
     }
     __syncthreads();  // first hidden layer complete
+#ifdef MC_TIMELINE
+    if (stamp) tln[2] = wall_clock64();
+#endif
 #pragma unroll
     for (int k = 0; k < WW; ++k) sh.hist[lane][wave * WW + k] = 0u;
     if (da_on) {
-        float o0 = 0.f, o1 = 0.f;
-#pragma unroll 1
-        for (int hc = wave * U; hc < wave * U + U; hc += UC) {
-            float a0[UC], a1[UC];
+        da_f32x16 acc[4];
 #pragma unroll
-            for (int u = 0; u < UC; ++u) a0[u] = a1[u] = b2[hc + u];
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+        const uint16_t* arow_h = h1 + amover * H1S + apos * kDaHid;
 #pragma unroll 2
-            for (int k = 0; k < kDaHid; k += 2) {
-                const uint32_t v0 = *reinterpret_cast<const uint32_t*>(&h1[lane * H1S + k]);
-                const uint32_t v1 = *reinterpret_cast<const uint32_t*>(&h1[lane * H1S + kDaHid + k]);
-                const float x0a = __builtin_bit_cast(float, v0 << 16), x0b = __builtin_bit_cast(float, v0 & 0xFFFF0000u);
-                const float x1a = __builtin_bit_cast(float, v1 << 16), x1b = __builtin_bit_cast(float, v1 & 0xFFFF0000u);
-                const float* wa = W2 + k * kDaHid + hc;
-                const float* wb = wa + kDaHid;
+        for (int j = 0; j < kDaHid / 8; ++j) {
+            const uint32_t lo = *reinterpret_cast<const uint32_t*>(arow_h + 8 * j + kq);
+            const uint32_t hi = *reinterpret_cast<const uint32_t*>(arow_h + 8 * j + kq + 2);
+            uint2 av;
+            av.x = lo;
+            av.y = hi;
 #pragma unroll
-                for (int u = 0; u < UC; ++u) {
-                    a0[u] = __builtin_fmaf(x0b, wb[u], __builtin_fmaf(x0a, wa[u], a0[u]));
-                    a1[u] = __builtin_fmaf(x1b, wb[u], __builtin_fmaf(x1a, wa[u], a1[u]));
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < UC; ++u) {
-                o0 = __builtin_fmaf(bf16_round(a0[u] > 0.f ? a0[u] : 0.f), w3[hc + u], o0);
-                o1 = __builtin_fmaf(bf16_round(a1[u] > 0.f ? a1[u] : 0.f), w3[hc + u], o1);
+            for (int t = 0; t < 4; ++t) {
+                const uint2 bv = bfrag(1, 32 * t + bcol, 8 * j + kq);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(__builtin_bit_cast(da_bf16x4, av),
+                                                                  __builtin_bit_cast(da_bf16x4, bv), acc[t], 0, 0, 0);
             }
         }
-        sh.part_out[wave][0][lane] = o0;
-        sh.part_out[wave][1][lane] = o1;
+        // last layer: sum over the columns of bf16(relu(Z2 + b2)) w3
+        float part[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) part[i] = 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int col = 32 * t + (lane & 31);
+            const float bias = wload(oB2 + col), wc = wload(oW3 + col);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const float z = acc[t][i] + bias;
+                part[i] = __builtin_fmaf(bf16_round(z > 0.f ? z : 0.f), wc, part[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+#pragma unroll
+            for (int d = 1; d < 32; d <<= 1) part[i] += __shfl_xor(part[i], d, 64);
+        }
+        if ((lane & 31) == 0) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) outs[wave * 32 + 8 * (i / 4) + 4 * (lane >> 5) + (i % 4)] = part[i];
+        }
     }
-    __syncthreads();  // partial outputs complete; the candidate space is free again
+    __syncthreads();  // outputs complete; the candidate space is free again
+#ifdef MC_TIMELINE
+    if (stamp) tln[3] = wall_clock64();
+#endif
     if (da_on && wave == 0) {
-        const float b3 = cd.da_w[kDaParams - 1];
-        float o0 = b3, o1 = b3;
-#pragma unroll
-        for (int w = 0; w < M; ++w) {
-            o0 += sh.part_out[w][0][lane];
-            o1 += sh.part_out[w][1][lane];
-        }
+        const float b3 = wload(kDaParams - 1);
+        const float o0 = b3 + outs[lane], o1 = b3 + outs[64 + lane];
         sh.deh[lane] = cd.lB * ((double)o1 - (double)o0);
     }
 }
@@ -726,6 +794,16 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
     // the delayed-acceptance switch is constant during a launch (the drift
     // monitor changes it between launches)
     const bool da_on = DA && cd.da != nullptr && cd.da->active != 0 && cd.da_w != nullptr;
+    if constexpr (SweepShared<T, M, DA>::kWtsLds) {
+        if (da_on) {
+            static_assert(kDaIn == kDaHid, "both matrices are 128 x 128");
+            for (int k = threadIdx.x; k < 2 * kDaHid * kDaIn / 4; k += 64 * M) {
+                const int row = k / (kDaIn / 4), c4 = k % (kDaIn / 4);  // row of the two stacked matrices
+                const uint16_t* src = row < kDaHid ? cd.da_w1b + row * kDaIn : cd.da_w2b + (row - kDaHid) * kDaIn;
+                *reinterpret_cast<uint2*>(&sh.wts[row][4 * c4]) = *reinterpret_cast<const uint2*>(src + 4 * c4);
+            }
+        }
+    }
     __syncthreads();
 
     WgCounters ctr;
@@ -959,7 +1037,7 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
             if constexpr (DA) {
                 const uint64_t cb = __ballot(conf);
                 if (lane == 0) sh.part_conf[wave] = cb;
-                da_network<T, M>(sh, cd, wave, lane, da_on, s * (int64_t)cd.n + ion, ion < cd.n);
+                da_network<T, M>(sh, cd, wave, lane, da_on, s * (int64_t)cd.n + ion, ion < cd.n, g);
             }
             sh.part_s[wave][lane] = S;
             {
