@@ -46,6 +46,18 @@ template <> struct Prec<float> {
     static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
     // operands are never NaN here: one v_min instruction
     static __device__ __forceinline__ float min(float a, float b) { return __builtin_fminf(a, b); }
+    // fused multiply-add where the product is exact (a multiplier of 0 or 1)
+    static __device__ __forceinline__ float fma_exact(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    // 1.0f if bit b of the wave-uniform word w is set, else 0.0f, formed on
+    // the scalar unit (bit-field extract, then a multiply by the bit pattern
+    // of 1.0f) so that it can feed a vector multiply-add as a scalar operand
+    template <int B>
+    static __device__ __forceinline__ float unit_if_bit(uint32_t w) {
+        static_assert(B >= 0 && B < 32, "bit index");
+        float m;
+        asm("s_bfe_u32 %0, %1, %2\n\ts_mul_i32 %0, %0, 0x3f800000" : "=s"(m) : "s"(w), "n"((1 << 16) | B) : "scc");
+        return m;
+    }
 };
 
 template <> struct Prec<double> {
@@ -58,6 +70,13 @@ template <> struct Prec<double> {
     // the double path keeps the textbook rounding: product, then sum
     static __device__ __forceinline__ double fma(double a, double b, double c) { return a * b + c; }
     static __device__ __forceinline__ double min(double a, double b) { return __builtin_fmin(a, b); }
+    // fused multiply-add where the product is exact (a multiplier of 0 or 1):
+    // the same result as the separately rounded form
+    static __device__ __forceinline__ double fma_exact(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    template <int B>
+    static __device__ __forceinline__ double unit_if_bit(uint32_t w) {
+        return ((w >> B) & 1u) ? 1.0 : 0.0;
+    }
 };
 
 template <typename T>

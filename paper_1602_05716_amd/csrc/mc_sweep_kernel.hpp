@@ -41,6 +41,8 @@
 //     accesses only).
 #pragma once
 
+#include <utility>
+
 #include "mc_device.hpp"
 
 namespace mcdev {
@@ -269,30 +271,35 @@ __device__ __forceinline__ void wait_lds_at_least(int* flag, int want, const Ctl
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// sum_j [bit j of mask] row[j] over the 64 partners, branch free: the row is
-// read with 16-byte loads and each value is ANDed with an all-ones or
-// all-zeros word built from the (wave-uniform) mask bit.  Fixed order, four
+// sum_j [bit j of mask] row[j] over the 64 partners, branch free: the
+// (wave-uniform) mask is moved to scalar registers, each bit becomes a
+// scalar 0 or 1 and the row value is multiply-added with it -- one vector
+// instruction per partner (fma(v, 1, a) rounds exactly as a + v, and
+// fma(v, 0, a) = a).  The row is read with 16-byte loads.  Fixed order, four
 // independent accumulators: deterministic.
-__device__ __forceinline__ float masked_pick(float v, uint64_t mask, int j) {
-    const uint32_t keep = 0u - (uint32_t)((mask >> j) & 1ull);
-    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) & keep);
-}
-__device__ __forceinline__ double masked_pick(double v, uint64_t mask, int j) {
-    const uint64_t keep = 0ull - ((mask >> j) & 1ull);
-    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & keep);
+// partners J .. J + V - 1 of the row, then the rest (compile-time bit indices)
+template <typename T, int V, int J>
+__device__ __forceinline__ void masked_row_part(const T* __restrict__ row, uint32_t mlo, uint32_t mhi, T* a) {
+    if constexpr (J < kGroup) {
+        typedef T VT __attribute__((ext_vector_type(V)));
+        const VT v = *reinterpret_cast<const VT*>(row + J);
+        [&]<int... K>(std::integer_sequence<int, K...>) {
+            ((a[(J + K) & 3] = Prec<T>::fma_exact(
+                  v[K], Prec<T>::template unit_if_bit<(J + K) & 31>((J + K) < 32 ? mlo : mhi), a[(J + K) & 3])),
+             ...);
+        }(std::make_integer_sequence<int, V>{});
+        masked_row_part<T, V, J + V>(row, mlo, mhi, a);
+    }
 }
 
 template <typename T>
 __device__ __forceinline__ T masked_row_sum(const T* __restrict__ row, uint64_t mask) {
     constexpr int V = 16 / (int)sizeof(T);  // values per 16-byte read
     typedef T VT __attribute__((ext_vector_type(V)));
+    const uint32_t mlo = __builtin_amdgcn_readfirstlane((uint32_t)mask);
+    const uint32_t mhi = __builtin_amdgcn_readfirstlane((uint32_t)(mask >> 32));
     T a[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int j = 0; j < kGroup; j += V) {
-        const VT v = *reinterpret_cast<const VT*>(row + j);
-#pragma unroll
-        for (int k = 0; k < V; ++k) a[(j + k) & 3] += masked_pick(v[k], mask, j + k);
-    }
+    masked_row_part<T, V, 0>(row, mlo, mhi, a);
     return (a[0] + a[1]) + (a[2] + a[3]);
 }
 
@@ -358,7 +365,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
 
 #ifdef MC_TIMELINE
     // diagnostic build only: per-group wall-clock stamps in the dE trace buffer
-    uint64_t tl0 = wall_clock64(), tl1 = 0, tl2 = 0, tl3 = 0;
+    uint64_t tl0 = wall_clock64(), tl1 = 0, tl2 = 0, tl3 = 0, tl4 = 0, tl5 = 0;
 #endif
     // the waves' partial sums
     wait_lds_at_least(&sh.ready, M, ctl);
@@ -469,6 +476,9 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
             ovb |= ((r.acc & ovtb[kb]) | (~r.acc & ovob[kb])) != 0;
         }
     }
+#ifdef MC_TIMELINE
+    tl4 = wall_clock64();
+#endif
     if (early) {
         // exact energy change of the (already decided) trials
         const T own = acc ? masked_row_sum<T>(sh.c_own[lane], acc) : (T)0;
@@ -492,6 +502,9 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
             ++it;
         }
         acc = nacc;
+#ifdef MC_TIMELINE
+        tl5 = wall_clock64();
+#endif
         publish_group<T>(rec_r, pos_r, g, s, npad, ion, acc, dec, xi, yi, zi, txi, tyi, tzi);
 #ifdef MC_TIMELINE
         tl3 = wall_clock64();
@@ -514,6 +527,11 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
         tl[1] = tl1;
         tl[2] = tl2;
         tl[3] = tl3;
+        if (!DA) {  // the network phase uses the other four slots
+            tl[4] = tl4;
+            tl[5] = tl5;
+            tl[6] = (uint64_t)it;
+        }
     }
 #endif
 
