@@ -87,7 +87,7 @@ typedef struct mc_options {
     uint32_t chain_id;      /* Philox counter word 2, default 0                    */
     void* hip_stream;       /* hipStream_t to enqueue on (e.g. a PyTorch stream);
                                NULL = a stream owned by the handle                 */
-    int32_t band;           /* look-ahead band width in 64-ion groups (0..2),
+    int32_t band;           /* look-ahead band width in 64-ion groups (0..4),
                                -1 = automatic; affects speed only                  */
     int32_t waves;          /* waves per workgroup (4 or 8), 0 = automatic         */
     int32_t workgroups;     /* workgroups serving the chain, 0 = automatic         */

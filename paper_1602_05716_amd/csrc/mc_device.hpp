@@ -12,7 +12,7 @@ namespace mcdev {
 
 constexpr int kGroup = 64;   // movers per group = lanes of one wavefront
 constexpr int kRing = 1024;  // group records kept per chain
-constexpr int kMaxBand = 2;  // largest look-ahead band, in groups
+constexpr int kMaxBand = 4;  // largest look-ahead band, in groups
 
 // Per-group record published by the workgroup that decided the group; one
 // 16-byte transaction, so the tag and the accept mask are read together.
@@ -48,16 +48,6 @@ template <> struct Prec<float> {
     static __device__ __forceinline__ float min(float a, float b) { return __builtin_fminf(a, b); }
     // fused multiply-add where the product is exact (a multiplier of 0 or 1)
     static __device__ __forceinline__ float fma_exact(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-    // 1.0f if bit b of the wave-uniform word w is set, else 0.0f, formed on
-    // the scalar unit (bit-field extract, then a multiply by the bit pattern
-    // of 1.0f) so that it can feed a vector multiply-add as a scalar operand
-    template <int B>
-    static __device__ __forceinline__ float unit_if_bit(uint32_t w) {
-        static_assert(B >= 0 && B < 32, "bit index");
-        float m;
-        asm("s_bfe_u32 %0, %1, %2\n\ts_mul_i32 %0, %0, 0x3f800000" : "=s"(m) : "s"(w), "n"((1 << 16) | B) : "scc");
-        return m;
-    }
 };
 
 template <> struct Prec<double> {
@@ -73,10 +63,6 @@ template <> struct Prec<double> {
     // fused multiply-add where the product is exact (a multiplier of 0 or 1):
     // the same result as the separately rounded form
     static __device__ __forceinline__ double fma_exact(double a, double b, double c) { return __builtin_fma(a, b, c); }
-    template <int B>
-    static __device__ __forceinline__ double unit_if_bit(uint32_t w) {
-        return ((w >> B) & 1u) ? 1.0 : 0.0;
-    }
 };
 
 template <typename T>
@@ -187,6 +173,24 @@ __device__ __forceinline__ void raise_timeout(const Ctl& ctl) {
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Bookkeeping of one bounded wait.  The clock is read on every poll; the
+// abort flag -- a single word that every waiting wave of the launch would
+// otherwise read on every poll -- on every 32nd only.
+struct PollGuard {
+    uint64_t t0;
+    uint32_t k;
+    __device__ __forceinline__ PollGuard() : t0(wall_clock64()), k(0) {}
+    // true when the wait has to end: abort raised elsewhere, or time-out here
+    __device__ __forceinline__ bool stop(const Ctl& ctl) {
+        if ((++k & 31u) == 0u && abort_raised(ctl)) return true;
+        if (wall_clock64() - t0 > ctl.timeout_ticks) {
+            raise_timeout(ctl);
+            return true;
+        }
+        return false;
+    }
+};
+
 // Waits for the record of group gp and returns it.  A record only carries the
 // group's accept mask (positions carry their own version tags).  Readers are
 // at most a few groups behind the newest publication, far fewer than the
@@ -194,7 +198,7 @@ __device__ __forceinline__ void raise_timeout(const Ctl& ctl) {
 __device__ __forceinline__ GroupRec wait_rec(__amdgpu_buffer_rsrc_t rr, int64_t gp, const Ctl& ctl) {
     const uint32_t slot = (uint32_t)(gp & (kRing - 1));
     const uint32_t want = (uint32_t)(gp + 1);
-    const uint64_t t0 = wall_clock64();
+    PollGuard pg;
     for (;;) {
         const GroupRec r = load_rec(rr, slot);
         const int32_t ahead = (int32_t)(r.tag - want);
@@ -210,11 +214,7 @@ __device__ __forceinline__ GroupRec wait_rec(__amdgpu_buffer_rsrc_t rr, int64_t 
                                                  __HIP_MEMORY_SCOPE_AGENT);
             return r;
         }
-        if (abort_raised(ctl)) return r;
-        if (wall_clock64() - t0 > ctl.timeout_ticks) {
-            raise_timeout(ctl);
-            return r;
-        }
+        if (pg.stop(ctl)) return r;
         __builtin_amdgcn_s_sleep(1);
     }
 }

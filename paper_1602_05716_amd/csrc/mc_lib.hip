@@ -362,7 +362,7 @@ void setup_chain(Chain& c, const mc_chain_spec& sp, const mc_options& opt) {
         c.type[i] = (int32_t)(it - c.species.begin());
         c.n_of_type[c.type[i]] += 1;
     }
-    c.band = opt.band >= 0 ? opt.band : 2;
+    c.band = opt.band >= 0 ? opt.band : kMaxBand;
     c.band = std::min(c.band, std::min(kMaxBand, c.nb - 1));
     c.trace_cap = opt.trace_moves;
 }

@@ -41,8 +41,6 @@
 //     accesses only).
 #pragma once
 
-#include <utility>
-
 #include "mc_device.hpp"
 
 namespace mcdev {
@@ -123,6 +121,15 @@ struct ChainDesc {
 // 16-byte halves {x, y}, {z, version}; the writer drains the first half
 // before storing the second and the reader validates the second half before
 // loading the first.
+// Pause between two polls of a global-memory slot: the shortest sleep, or
+// about 0.85 us (32 x 64 clocks) for a patient reader.
+__device__ __forceinline__ void poll_pause(bool patient) {
+    if (patient)
+        __builtin_amdgcn_s_sleep(32);
+    else
+        __builtin_amdgcn_s_sleep(1);
+}
+
 template <typename T> struct PosIO;
 
 template <> struct PosIO<float> {
@@ -136,22 +143,20 @@ template <> struct PosIO<float> {
         Rec v{x, y, z, ver};
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, idx * 16u, 0, kCoherent);
     }
-    // loads slot idx until its version is `ver` (all lanes with `active`)
+    // loads slot idx until its version is `ver` (all lanes with `active`);
+    // a patient reader (one whose result is not needed for several groups)
+    // polls about once a microsecond instead of back to back
     static __device__ __forceinline__ Rec load_valid(__amdgpu_buffer_rsrc_t r, uint32_t idx, uint32_t ver,
-                                                     bool active, const Ctl& ctl) {
+                                                     bool active, const Ctl& ctl, bool patient = false) {
         Rec v{0.f, 0.f, 0.f, ver};
         if (active) v = load(r, idx);
         if (__ballot(active && v.ver != ver) == 0ull) return v;
-        const uint64_t t0 = wall_clock64();
+        PollGuard pg;
         for (;;) {
-            __builtin_amdgcn_s_sleep(1);
+            poll_pause(patient);
             if (active && v.ver != ver) v = load(r, idx);
             if (__ballot(active && v.ver != ver) == 0ull) break;
-            if (abort_raised(ctl)) break;
-            if (wall_clock64() - t0 > ctl.timeout_ticks) {
-                raise_timeout(ctl);
-                break;
-            }
+            if (pg.stop(ctl)) break;
         }
         return v;
     }
@@ -177,20 +182,16 @@ template <> struct PosIO<double> {
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, hi), r, idx * 32u + 16u, 0, kCoherent);
     }
     static __device__ __forceinline__ Rec load_valid(__amdgpu_buffer_rsrc_t r, uint32_t idx, uint32_t ver,
-                                                     bool active, const Ctl& ctl) {
+                                                     bool active, const Ctl& ctl, bool patient = false) {
         Hi h{0.0, ver, 0u};
         if (active) h = load_hi(r, idx);
         if (__ballot(active && h.ver != ver) != 0ull) {
-            const uint64_t t0 = wall_clock64();
+            PollGuard pg;
             for (;;) {
-                __builtin_amdgcn_s_sleep(1);
+                poll_pause(patient);
                 if (active && h.ver != ver) h = load_hi(r, idx);
                 if (__ballot(active && h.ver != ver) == 0ull) break;
-                if (abort_raised(ctl)) break;
-                if (wall_clock64() - t0 > ctl.timeout_ticks) {
-                    raise_timeout(ctl);
-                    break;
-                }
+                if (pg.stop(ctl)) break;
             }
         }
         drain_memory();  // the high half is validated before the low half is read
@@ -205,9 +206,16 @@ template <int P> struct SliceBits;
 template <> struct SliceBits<8> { using type = uint8_t; };
 template <> struct SliceBits<16> { using type = uint16_t; };
 
-// Band groups with candidate corrections in LDS: kMaxBand, or 1 for the
+// Band groups with both-outcome candidates: kMaxBand, or 1 for the
 // delayed-acceptance kernels (whose LDS also holds neighbour histograms).
+// Only group g-1 goes to the chain wave; the accept masks of the older band
+// groups are out before the compute waves finish, and each wave resolves its
+// own slice of their candidates itself.
 template <bool DA> constexpr int kBandSlots = DA ? 1 : kMaxBand;
+// A compute wave waiting for a partner group more than this many groups
+// before its target polls patiently: the chain publishes about one group
+// every two microseconds, far slower than a tile takes to compute.
+constexpr int kPatientDistance = 6;
 
 template <typename T, int M, bool DA = false>
 struct SweepShared {
@@ -223,16 +231,20 @@ struct SweepShared {
     double part_s[M][kGroup];   // partial sums over each wave's partners
     uint64_t part_ov[M];        // overlap ballots over final partners
     T part_pn[M][2][kGroup];    // per wave: sums of the positive / negative
-                                // corrections still unknown (band groups, own group)
-    SB ovo_own[M][kGroup];      // own group, j < i: overlap with j's old position
-    SB ovt_own[M][kGroup];      //                   overlap with j's trial position
-    SB ovo_b[KB][M][kGroup];    // group g-1-kb: overlap with j's old / trial position
-    SB ovt_b[KB][M][kGroup];
+                                // corrections still unknown (group g-1, own group)
+    // overlap bits per mover i, one 64-bit word over the partners j in which
+    // wave w fills the slice of its own partners (bits w P .. w P + P - 1)
+    static_assert(sizeof(SB) * M == 8, "the waves' slices tile a 64-bit word");
+    alignas(8) SB ovo_own[kGroup][M];    // own group, j < i: overlap with j's old position
+    alignas(8) SB ovt_own[kGroup][M];    //                   overlap with j's trial position
+    alignas(8) SB ovo_b[kGroup][M];      // group g-1: overlap with j's old / trial position
+    alignas(8) SB ovt_b[kGroup][M];
     // corrections, one padded row per mover i (16-byte reads of 4 partners
     // are free of bank conflicts)
     static constexpr int CS = kGroup + (sizeof(T) == 4 ? 4 : 2);
     T c_own[kGroup][CS];           // own group [mover i][partner j]
-    T c_b[KB][kGroup][CS];         // group g-1-kb [mover i][partner j]
+    T c_b[kGroup][CS];             // group g-1 [mover i][partner j]
+    T fac[kGroup];                 // chain wave: 0/1 factors of a row sum's mask
     int ready;                  // compute waves done filling the hand-off for the current target
     int consumed;               // local target index + 1 the chain wave last released
     // delayed acceptance: per mover, byte histograms of neighbour distances at
@@ -254,52 +266,50 @@ struct SweepShared {
     __device__ uint16_t* h1() { return reinterpret_cast<uint16_t*>(&c_own[0][0]); }
 };
 
+// The 64-bit word of overlap bits that the waves' slices tile.
+template <typename SB, int M>
+__device__ __forceinline__ uint64_t slice_word(const SB (&w)[M]) {
+    uint64_t v;
+    __builtin_memcpy(&v, &w[0], sizeof(v));
+    return v;
+}
+
 // Bounded LDS wait used between the compute waves and the chain wave.
 __device__ __forceinline__ void wait_lds_at_least(int* flag, int want, const Ctl& ctl) {
     if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < want) {
-        const uint64_t t0 = wall_clock64();
+        PollGuard pg;
         for (;;) {
             __builtin_amdgcn_s_sleep(1);
             if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= want) break;
-            if (abort_raised(ctl)) break;
-            if (wall_clock64() - t0 > ctl.timeout_ticks) {
-                raise_timeout(ctl);
-                break;
-            }
+            if (pg.stop(ctl)) break;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// sum_j [bit j of mask] row[j] over the 64 partners, branch free: the
-// (wave-uniform) mask is moved to scalar registers, each bit becomes a
-// scalar 0 or 1 and the row value is multiply-added with it -- one vector
-// instruction per partner (fma(v, 1, a) rounds exactly as a + v, and
-// fma(v, 0, a) = a).  The row is read with 16-byte loads.  Fixed order, four
-// independent accumulators: deterministic.
-// partners J .. J + V - 1 of the row, then the rest (compile-time bit indices)
-template <typename T, int V, int J>
-__device__ __forceinline__ void masked_row_part(const T* __restrict__ row, uint32_t mlo, uint32_t mhi, T* a) {
-    if constexpr (J < kGroup) {
-        typedef T VT __attribute__((ext_vector_type(V)));
-        const VT v = *reinterpret_cast<const VT*>(row + J);
-        [&]<int... K>(std::integer_sequence<int, K...>) {
-            ((a[(J + K) & 3] = Prec<T>::fma_exact(
-                  v[K], Prec<T>::template unit_if_bit<(J + K) & 31>((J + K) < 32 ? mlo : mhi), a[(J + K) & 3])),
-             ...);
-        }(std::make_integer_sequence<int, V>{});
-        masked_row_part<T, V, J + V>(row, mlo, mhi, a);
-    }
-}
-
+// sum_j [bit j of mask] row[j] over the 64 partners, branch free.  The
+// (wave-uniform) mask is spread over the lanes as 0/1 factors in LDS, one
+// per partner, written lane-parallel; every lane then reads the factors as
+// broadcasts beside its own row and multiply-adds: one vector instruction
+// per partner (fma(1, v, a) rounds exactly as a + v, and fma(0, v, a) = a).
+// 16-byte loads; fixed order, four independent accumulators: deterministic.
+// Only the chain wave calls it, on its own factor row.
 template <typename T>
-__device__ __forceinline__ T masked_row_sum(const T* __restrict__ row, uint64_t mask) {
+__device__ __forceinline__ T masked_row_sum(const T* __restrict__ row, T* fac, uint64_t mask) {
     constexpr int V = 16 / (int)sizeof(T);  // values per 16-byte read
     typedef T VT __attribute__((ext_vector_type(V)));
-    const uint32_t mlo = __builtin_amdgcn_readfirstlane((uint32_t)mask);
-    const uint32_t mhi = __builtin_amdgcn_readfirstlane((uint32_t)(mask >> 32));
+    const int lane = threadIdx.x & 63;
+    wave_lds_sync();  // the previous call's factor reads come first
+    fac[lane] = (T)(uint32_t)((mask >> lane) & 1ull);
+    wave_lds_sync();
     T a[4] = {0, 0, 0, 0};
-    masked_row_part<T, V, 0>(row, mlo, mhi, a);
+#pragma unroll
+    for (int j = 0; j < kGroup; j += V) {
+        const VT v = *reinterpret_cast<const VT*>(row + j);
+        const VT f = *reinterpret_cast<const VT*>(fac + j);
+#pragma unroll
+        for (int k = 0; k < V; ++k) a[(j + k) & 3] = Prec<T>::fma_exact(f[k], v[k], a[(j + k) & 3]);
+    }
     return (a[0] + a[1]) + (a[2] + a[3]);
 }
 
@@ -328,21 +338,52 @@ __device__ __forceinline__ void publish_group(__amdgpu_buffer_rsrc_t rec_r, __am
 // of the pair terms: combine the waves' hand-off, decide the group (from the
 // bounds, or after the band groups' accept masks by fixed-point iteration)
 // and publish.
+// Per-mover inputs of the chain step that do not depend on the other moves,
+// formed at the start of the target's work, long before its decisions are
+// due: the hard-wall test of the trial position (Sec. 5.2), the Metropolis
+// threshold -log(u3) (u3 < exp(-dE) is evaluated as dE < -log(u3); the two
+// forms can only disagree within rounding of the threshold itself, and
+// dE <= 0 always accepts), and l_B q_i.
+struct MoverInputs {
+    bool wall;
+    double thr;
+    double lq;
+};
+
+template <typename T>
+__device__ __forceinline__ MoverInputs mover_inputs(const ChainDesc& cd, int ion, T qi, T txi, T tyi, T tzi,
+                                                    uint32_t w3) {
+    MoverInputs mi;
+    const double a = cd.wall_a[ion];
+    const double X = (double)txi, Y = (double)tyi, Z = (double)tzi;
+    int wall = (X * X + Y * Y + Z * Z > a * a) ? 1 : 0;
+    double thr = -log(accept_uniform(w3));
+    double lq = cd.lB * (double)qi;
+    // evaluated here, not sunk to their first use behind the hand-off wait
+    asm volatile("" : "+v"(wall), "+v"(thr), "+v"(lq));
+    mi.wall = wall != 0;
+    mi.thr = thr;
+    mi.lq = lq;
+    return mi;
+}
+
 // Counters of one workgroup, added to the chain's stats at the end.
 struct WgCounters {
     unsigned long long moves = 0, acc = 0, wall = 0, ov = 0, iters = 0, early = 0;
     unsigned long long da_moves = 0, conflicts = 0, s1_rej = 0, s2_rej = 0, s1_pass = 0;
 };
 
+#ifdef MC_TIMELINE
+constexpr int kTlSlots = 32;  // diagnostic build: stamps per group in the dE trace buffer
+#endif
+
 template <typename T, int M, bool DA>
 __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const ChainDesc& cd,
                                            __amdgpu_buffer_rsrc_t pos_r, __amdgpu_buffer_rsrc_t rec_r,
-                                           const T* __restrict__ charge, int64_t g_begin, int64_t g, int t,
-                                           T xi, T yi, T zi, T txi, T tyi, T tzi, uint32_t w3, bool da_active,
+                                           int64_t g_begin, int64_t g, int t,
+                                           T xi, T yi, T zi, T txi, T tyi, T tzi, const MoverInputs& mi, bool da_active,
                                            const Ctl& ctl, WgCounters& ctr)
 {
-    constexpr int P = kGroup / M;
-    constexpr int KB = SweepShared<T, M, DA>::KB;
     const int lane = threadIdx.x & 63;
     const int n = cd.n, nb = cd.nb, band = cd.band;
     const int npad = nb * kGroup;
@@ -350,22 +391,12 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
     const int b = (int)(g - s * nb);
     const int ion = b * kGroup + lane;
     const bool valid = ion < n;
-    const double qd = (double)charge[ion];
-    bool wall;
-    {
-        const double a = cd.wall_a[ion];
-        const double X = (double)txi, Y = (double)tyi, Z = (double)tzi;
-        const double r2 = X * X + Y * Y + Z * Z;
-        wall = r2 > a * a;
-    }
-    // Metropolis threshold: u3 < exp(-dE) is evaluated as dE < -log(u3), which
-    // is computed before the critical wait (the two forms can only disagree
-    // within rounding of the threshold itself; dE <= 0 always accepts)
-    const double thr = -log(accept_uniform(w3));
+    const bool wall = mi.wall;
+    const double thr = mi.thr;
 
 #ifdef MC_TIMELINE
     // diagnostic build only: per-group wall-clock stamps in the dE trace buffer
-    uint64_t tl0 = wall_clock64(), tl1 = 0, tl2 = 0, tl3 = 0, tl4 = 0, tl5 = 0;
+    uint64_t tl0 = wall_clock64(), tl1 = 0, tl2 = 0, tl3 = 0, tl4 = 0, tl5 = 0, tl6 = 0, tlA = 0, tlB = 0, tlC = 0;
 #endif
     // the waves' partial sums
     wait_lds_at_least(&sh.ready, M, ctl);
@@ -373,26 +404,24 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
     tl1 = wall_clock64();
 #endif
     double St = 0.0;
-    uint64_t ovo = 0, ovt = 0, ovob[KB], ovtb[KB];
+    uint64_t ovo = 0, ovt = 0, ovob = 0, ovtb = 0;
     bool ovb = false;
     T cp = 0, cn = 0;
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) ovob[kb] = ovtb[kb] = 0;
 #pragma unroll
     for (int w = 0; w < M; ++w) {
         cp += sh.part_pn[w][0][lane];
         cn += sh.part_pn[w][1][lane];
         St += sh.part_s[w][lane];
         ovb |= ((sh.part_ov[w] >> lane) & 1ull) != 0;
-        ovo |= (uint64_t)sh.ovo_own[w][lane] << (w * P);
-        ovt |= (uint64_t)sh.ovt_own[w][lane] << (w * P);
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-            ovob[kb] |= (uint64_t)sh.ovo_b[kb][w][lane] << (w * P);
-            ovtb[kb] |= (uint64_t)sh.ovt_b[kb][w][lane] << (w * P);
-        }
     }
+    ovo = slice_word(sh.ovo_own[lane]);
+    ovt = slice_word(sh.ovt_own[lane]);
+    ovob = slice_word(sh.ovo_b[lane]);
+    ovtb = slice_word(sh.ovt_b[lane]);
 
+#ifdef MC_TIMELINE
+    tlA = wall_clock64();
+#endif
     // Delayed acceptance (two-stage rule): a move without a conflict passes
     // stage 1 when dEh <= 0 or u3 < exp(-dEh), i.e. dEh < thr, and is then
     // accepted when dE - dEh <= 0 or u2 < exp(-(dE - dEh)), i.e. when
@@ -430,7 +459,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
     // Otherwise: wait for the band groups and iterate the sequential rule to
     // its fixed point.
     __builtin_amdgcn_s_setprio(3);
-    const double lq = cd.lB * qd;
+    const double lq = mi.lq;
     const bool can = valid && !wall && !ovb;
     uint64_t acc = 0;
     double dE = 0.0;
@@ -444,12 +473,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
         const double e_hi = lq >= 0 ? lq * hi : lq * lo;
         const double span = (double)(cp - cn);
         const double margin = fabs(lq) * (1e-4 * span + 1e-9 * (fabs(St) + 1.0)) + 1e-12;
-        uint64_t ov_sure = 0, ov_flip = ovo ^ ovt;
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-            ov_sure |= ovob[kb] & ovtb[kb];
-            ov_flip |= ovob[kb] ^ ovtb[kb];
-        }
+        const uint64_t ov_sure = ovob & ovtb, ov_flip = (ovo ^ ovt) | (ovob ^ ovtb);
         const bool reject_sure = !can || s1_rej || ov_sure != 0 || (ovo & ovt) != 0;
         const bool accept_sure = !reject_sure && ov_flip == 0 && e_hi < thr_eff - margin;
         const bool sure = reject_sure || accept_sure || (ov_flip == 0 && e_lo >= thr_eff + margin);
@@ -463,45 +487,83 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
 #endif
         }
     }
-    // band corrections, oldest group first
-    double corr = 0.0;
-#pragma unroll
-    for (int kb = KB - 1; kb >= 0; --kb) {
-        if (kb < band) {
-            const GroupRec r = wait_rec(rec_r, g - 1 - kb, ctl);
 #ifdef MC_TIMELINE
-            if (kb == 0) tl2 = wall_clock64();
+    tlB = wall_clock64();
 #endif
-            corr += (double)masked_row_sum<T>(sh.c_b[kb][lane], r.acc);
-            ovb |= ((r.acc & ovtb[kb]) | (~r.acc & ovob[kb])) != 0;
+    // One evaluation of the sequential rule inside the group given an accept
+    // mask `a` of the own group (row sum `own`): the decisions every lane
+    // would take.  Lane i depends on lanes j < i only (the system is lower
+    // triangular), so the iteration a <- rule(a) reaches the one fixed point
+    // from any start within kGroup + 1 evaluations, and a mask that the rule
+    // reproduces is that fixed point.
+    auto rule = [&](double Sx, bool canx, uint64_t a, T own) {
+        const bool ovown = ((a & ovt) | (~a & ovo)) != 0;
+        dE = lq * (Sx + (double)own);
+        dec = canx && !ovown && (dE <= shift || dE < thr_eff);
+        return __ballot(dec);
+    };
+    // iterates from mask a (row sum own) to the fixed point
+    auto solve = [&](double Sx, bool canx, uint64_t a, T own) {
+        uint64_t na = rule(Sx, canx, a, own);
+        ++it;
+        while (na != a && it <= kGroup + 2) {
+            a = na;
+            own = masked_row_sum<T>(sh.c_own[lane], sh.fac, a);
+            na = rule(Sx, canx, a, own);
+            ++it;
         }
-    }
+        acc = na;
+        return own;
+    };
+    double corr = 0.0;  // band correction of group g-1
 #ifdef MC_TIMELINE
-    tl4 = wall_clock64();
+    tlC = wall_clock64();
 #endif
     if (early) {
+        if (band >= 1) {
+            const GroupRec r = wait_rec(rec_r, g - 1, ctl);
+#ifdef MC_TIMELINE
+            tl2 = wall_clock64();
+#endif
+            corr += (double)masked_row_sum<T>(sh.c_b[lane], sh.fac, r.acc);
+            ovb |= ((r.acc & ovtb) | (~r.acc & ovob)) != 0;
+        }
         // exact energy change of the (already decided) trials
-        const T own = acc ? masked_row_sum<T>(sh.c_own[lane], acc) : (T)0;
+        const T own = acc ? masked_row_sum<T>(sh.c_own[lane], sh.fac, acc) : (T)0;
         dE = lq * ((St + corr) + (double)own);
         it = 1;
     } else {
-        // sequential decisions inside the group by fixed-point iteration
-        St += corr;
-        const bool can2 = valid && !wall && !ovb;
-        dE = lq * St;
-        dec = can2 && (dE <= shift || dE < thr_eff);
-        it = 1;
-        uint64_t nacc = __ballot(dec);
-        while (nacc != acc && it <= kGroup + 1) {
-            acc = nacc;
-            const T own = masked_row_sum<T>(sh.c_own[lane], acc);
-            const bool ovown = ((acc & ovt) | (~acc & ovo)) != 0;
-            dE = lq * (St + (double)own);
-            dec = can2 && !ovown && (dE <= shift || dE < thr_eff);
-            nacc = __ballot(dec);
-            ++it;
+        // While group g-1's accept mask is on its way, the fixed point is
+        // solved for a guess of it (every move of g-1 rejected); once the
+        // mask is in, one evaluation with the true band correction confirms
+        // the guessed solution, or the iteration goes on from it.
+        T own = 0;
+        if (band >= 1) {
+            const bool can_g = valid && !wall && !ovb && ovob == 0;
+            own = solve(St + corr, can_g, 0, (T)0);
+            const uint64_t guess = acc;
+#ifdef MC_TIMELINE
+            tl6 = wall_clock64();
+#endif
+            const GroupRec r = wait_rec(rec_r, g - 1, ctl);
+#ifdef MC_TIMELINE
+            tl2 = wall_clock64();
+#endif
+            corr += (double)masked_row_sum<T>(sh.c_b[lane], sh.fac, r.acc);
+            ovb |= ((r.acc & ovtb) | (~r.acc & ovob)) != 0;
+#ifdef MC_TIMELINE
+            tl4 = wall_clock64();
+#endif
+            St += corr;
+            it = 0;
+            own = solve(St, valid && !wall && !ovb, guess, own);
+        } else {
+#ifdef MC_TIMELINE
+            tl2 = tl4 = wall_clock64();
+#endif
+            St += corr;
+            own = solve(St, valid && !wall && !ovb, 0, (T)0);
         }
-        acc = nacc;
 #ifdef MC_TIMELINE
         tl5 = wall_clock64();
 #endif
@@ -521,16 +583,20 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
 
     __builtin_amdgcn_s_setprio(0);
 #ifdef MC_TIMELINE
-    if (lane == 0 && 8 * (g + 1) <= cd.trace_cap) {
-        uint64_t* tl = (uint64_t*)cd.trace_de + 8 * g;
+    if (lane == 0 && kTlSlots * (g + 1) <= cd.trace_cap) {
+        uint64_t* tl = (uint64_t*)cd.trace_de + kTlSlots * g;
         tl[0] = tl0;
         tl[1] = tl1;
         tl[2] = tl2;
         tl[3] = tl3;
-        if (!DA) {  // the network phase uses the other four slots
+        {
             tl[4] = tl4;
             tl[5] = tl5;
-            tl[6] = (uint64_t)it;
+            tl[6] = tl6;
+            tl[7] = (uint64_t)it;
+            tl[8] = tlA;
+            tl[9] = tlB;
+            tl[10] = tlC;
         }
     }
 #endif
@@ -630,8 +696,8 @@ __device__ __forceinline__ void da_network(SweepShared<T, M, true>& sh, const Ch
                                            bool da_on, int64_t mv, bool valid, int64_t g) {
 #ifdef MC_TIMELINE
     // diagnostic build only: stamps of the network phase after the chain stamps
-    uint64_t* tln = (uint64_t*)cd.trace_de + 8 * g + 4;
-    const bool stamp = wave == 0 && lane == 0 && 8 * (g + 1) <= cd.trace_cap;
+    uint64_t* tln = (uint64_t*)cd.trace_de + kTlSlots * g + 11;
+    const bool stamp = wave == 0 && lane == 0 && kTlSlots * (g + 1) <= cd.trace_cap;
     if (stamp) tln[0] = wall_clock64();
 #else
     (void)g;
@@ -840,7 +906,13 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
             const T txi = trial_coord(xi, wd.x, D), tyi = trial_coord(yi, wd.y, D),
                     tzi = trial_coord(zi, wd.z, D);
             const T hi = UNIFORM_SIGMA ? hu : half[ion];
+            MoverInputs mi{};
+            if (wave == 0) mi = mover_inputs(cd, ion, qi, txi, tyi, tzi, wd.w);
 
+#ifdef MC_TIMELINE
+            if (!DA && wave == 0 && lane == 0 && kTlSlots * (g + 1) <= cd.trace_cap)
+                ((uint64_t*)cd.trace_de)[kTlSlots * g + 11] = wall_clock64();
+#endif
             double S = 0.0;     // sum_j q_j (1/|x~_i - x_j| - 1/|x_i - x_j|)
             bool ov = false;    // overlap with a partner whose position is final
             bool conf = false;  // delayed acceptance: a pending partner is near (conflict rule)
@@ -969,6 +1041,39 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
                 }
             }
 
+            // the candidates of group g-1 and of the own group for the chain
+            // wave: overlap slices, the sums of their positive and negative
+            // parts (bounds of the corrections still unknown) and the rows
+            auto hand_off_candidates = [&]() {
+                sh.ovo_own[lane][wave] = ovo_own;
+                sh.ovt_own[lane][wave] = ovt_own;
+                sh.ovo_b[lane][wave] = ovo_band[0];
+                sh.ovt_b[lane][wave] = ovt_band[0];
+                T cp = 0, cn = 0;
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    cp += c_band[0][m] > 0 ? c_band[0][m] : (T)0;
+                    cn += c_band[0][m] < 0 ? c_band[0][m] : (T)0;
+                    cp += c_own[m] > 0 ? c_own[m] : (T)0;
+                    cn += c_own[m] < 0 ? c_own[m] : (T)0;
+                }
+                sh.part_pn[wave][0][lane] = cp;
+                sh.part_pn[wave][1][lane] = cn;
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    sh.c_own[lane][wave * P + m] = c_own[m];
+                    sh.c_b[lane][wave * P + m] = c_band[0][m];  // zero when band = 0
+                }
+            };
+            if constexpr (!DA) {
+                // complete from here on: handed off now, off the critical
+                // path, once the chain wave has released the previous target
+                // (the delayed-acceptance kernels reuse this LDS for the
+                // network and hand off at the end)
+                wait_lds_at_least(&sh.consumed, t, ctl);
+                hand_off_candidates();
+            }
+
             // ---- decided partner groups g-nb+1 .. g-band-1, in stream order.  The next
             // tile is loaded speculatively while this one is computed (float path); a
             // record whose version is not the expected one yet is loaded again.
@@ -991,7 +1096,12 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
                     if (have_next && __ballot(lane < P && nxt.ver != (uint32_t)sp) == 0ull)
                         cur = nxt;
                     else
-                        cur = IO::load_valid(pos_r, (uint32_t)((sp & 1) * npad + j), (uint32_t)sp, lane < P, ctl);
+                        cur = IO::load_valid(pos_r, (uint32_t)((sp & 1) * npad + j), (uint32_t)sp, lane < P, ctl,
+                                             g - gp > kPatientDistance);
+#ifdef MC_TIMELINE
+                    if (!DA && gp == g_last && lane == 0 && kTlSlots * (g + 1) <= cd.trace_cap)
+                        ((uint64_t*)cd.trace_de)[kTlSlots * g + (wave == 0 ? 14 : 24 + wave)] = wall_clock64();
+#endif
                     if (lane < P) {
                         sh.st_old[wave][lane] = mk4<T>(cur.x, cur.y, cur.z, charge[j]);
                         if (!UNIFORM_SIGMA) sh.st_half[wave][lane] = half[j];
@@ -1048,58 +1158,65 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
                 }
                 if (UNIFORM_SIGMA) ov |= d2t_min < (hu + hu) * (hu + hu);
             }
+#ifdef MC_TIMELINE
+            if (!DA && wave == 0 && lane == 0 && kTlSlots * (g + 1) <= cd.trace_cap)
+                ((uint64_t*)cd.trace_de)[kTlSlots * g + 12] = wall_clock64();
+#endif
 
+            // ---- band groups older than g-1: their accept masks are out by
+            // now (published about one group after the last partner tile);
+            // this wave's slice of their candidates becomes final
+            GroupRec rb[KB];
+#pragma unroll
+            for (int kb = 1; kb < KB; ++kb)  // all loads in flight at once
+                if (kb < band) rb[kb] = load_rec(rec_r, (uint32_t)((g - 1 - kb) & (kRing - 1)));
+#pragma unroll
+            for (int kb = KB - 1; kb >= 1; --kb) {
+                if (kb < band) {
+                    const GroupRec r = rb[kb].tag == (uint32_t)(g - kb) ? rb[kb] : wait_rec(rec_r, g - 1 - kb, ctl);
+                    const uint32_t a = (uint32_t)(r.acc >> (wave * P));
+                    T sf = 0;
+                    SB hit = 0;
+#pragma unroll
+                    for (int m = 0; m < P; ++m) {
+                        const bool am = ((a >> m) & 1u) != 0;
+                        sf += am ? c_band[kb][m] : (T)0;
+                        hit |= am ? (ovt_band[kb] & (SB)(1u << m)) : (ovo_band[kb] & (SB)(1u << m));
+                    }
+                    S += (double)sf;
+                    ov |= hit != 0;
+                }
+            }
 
+#ifdef MC_TIMELINE
+            if (!DA && lane == 0 && kTlSlots * (g + 1) <= cd.trace_cap)
+                ((uint64_t*)cd.trace_de)[kTlSlots * g + (wave == 0 ? 13 : 20 + wave)] = wall_clock64();
+#endif
             // ---- hand off to the chain wave once it has released the previous target
-            wait_lds_at_least(&sh.consumed, t, ctl);
             if constexpr (DA) {
+                wait_lds_at_least(&sh.consumed, t, ctl);
                 const uint64_t cb = __ballot(conf);
                 if (lane == 0) sh.part_conf[wave] = cb;
                 da_network<T, M>(sh, cd, wave, lane, da_on, s * (int64_t)cd.n + ion, ion < cd.n, g);
             }
+            if constexpr (DA) hand_off_candidates();
             sh.part_s[wave][lane] = S;
             {
                 const uint64_t ob = __ballot(ov);
                 if (lane == 0) sh.part_ov[wave] = ob;
             }
-            sh.ovo_own[wave][lane] = ovo_own;
-            sh.ovt_own[wave][lane] = ovt_own;
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb) {
-                sh.ovo_b[kb][wave][lane] = ovo_band[kb];
-                sh.ovt_b[kb][wave][lane] = ovt_band[kb];
-            }
-            {
-                // candidate corrections are zero outside the band
-                T cp = 0, cn = 0;
-#pragma unroll
-                for (int m = 0; m < P; ++m) {
-#pragma unroll
-                    for (int kb = 0; kb < KB; ++kb) {
-                        cp += c_band[kb][m] > 0 ? c_band[kb][m] : (T)0;
-                        cn += c_band[kb][m] < 0 ? c_band[kb][m] : (T)0;
-                    }
-                    cp += c_own[m] > 0 ? c_own[m] : (T)0;
-                    cn += c_own[m] < 0 ? c_own[m] : (T)0;
-                }
-                sh.part_pn[wave][0][lane] = cp;
-                sh.part_pn[wave][1][lane] = cn;
-            }
-#pragma unroll
-            for (int m = 0; m < P; ++m) {
-                sh.c_own[lane][wave * P + m] = c_own[m];
-#pragma unroll
-                for (int kb = 0; kb < KB; ++kb)
-                    if (kb < band) sh.c_b[kb][lane][wave * P + m] = c_band[kb][m];
-            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             if (lane == 0)
                 __hip_atomic_fetch_add(&sh.ready, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#ifdef MC_TIMELINE
+            if (!DA && lane == 0 && wave < 4 && kTlSlots * (g + 1) <= cd.trace_cap)
+                ((uint64_t*)cd.trace_de)[kTlSlots * g + 16 + wave] = wall_clock64();
+#endif
 
             // ---- wave 0 finishes the group: decisions and publication
             if (wave == 0) {
-                chain_step<T, M, DA>(sh, cd, pos_r, rec_r, charge, g_begin, g, t, xi, yi, zi, txi, tyi, tzi,
-                                     wd.w, da_on, ctl, ctr);
+                chain_step<T, M, DA>(sh, cd, pos_r, rec_r, g_begin, g, t, xi, yi, zi, txi, tyi, tzi, mi, da_on,
+                                     ctl, ctr);
                 if (g == g_end - 1 && lane == 0) cd.clk[1] = wall_clock64();
             }
         }

@@ -61,7 +61,8 @@ def test_fp64_small_config_bit_exact(oracle):
 
 
 @pytest.mark.parametrize("n,band,waves", [(1, 0, 4), (2, 0, 4), (63, 0, 4), (64, 0, 8), (65, 1, 4),
-                                          (130, 2, 4), (257, 2, 8), (777, 2, 4)])
+                                          (130, 2, 4), (257, 2, 8), (777, 2, 4), (321, 3, 4), (777, 4, 8),
+                                          (1000, 4, 4)])
 def test_fp64_ragged_sizes_and_schedules(oracle, n, band, waves):
     """Ragged N (padding lanes), one to many groups, band 0..4, 4 or 8 waves."""
     if n == 1:
