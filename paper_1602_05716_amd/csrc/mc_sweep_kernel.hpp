@@ -208,10 +208,15 @@ template <> struct SliceBits<16> { using type = uint16_t; };
 
 // Band groups with both-outcome candidates: kMaxBand, or 1 for the
 // delayed-acceptance kernels (whose LDS also holds neighbour histograms).
-// Only group g-1 goes to the chain wave; the accept masks of the older band
-// groups are out before the compute waves finish, and each wave resolves its
-// own slice of their candidates itself.
+// The newest kChainSlots of them (g-1, g-2[, g-3]) go to the chain step
+// through LDS; the accept masks of the older ones are out before the compute
+// waves finish, and each wave resolves its own slice of their candidates
+// itself.  (The float kernels keep two slots: a third would no longer let
+// two workgroups share a CU's LDS.  The double kernels run one workgroup
+// per CU and take three.)
 template <bool DA> constexpr int kBandSlots = DA ? 1 : kMaxBand;
+template <typename T, int M, bool DA>
+constexpr int kChainSlots = DA ? 1 : (sizeof(T) == 4 ? 2 : 3);
 // A compute wave waiting for a partner group more than this many groups
 // before its target polls patiently: the chain publishes about one group
 // every two microseconds, far slower than a tile takes to compute.
@@ -222,6 +227,7 @@ struct SweepShared {
     using T4 = typename Prec<T>::T4;
     static constexpr int P = kGroup / M;
     static constexpr int KB = kBandSlots<DA>;
+    static constexpr int LC = kChainSlots<T, M, DA>;
     using SB = typename SliceBits<P>::type;
     // per compute wave: staging of the current partner slice {x, y, z, q}
     T4 st_old[M][P];
@@ -231,22 +237,29 @@ struct SweepShared {
     double part_s[M][kGroup];   // partial sums over each wave's partners
     uint64_t part_ov[M];        // overlap ballots over final partners
     T part_pn[M][2][kGroup];    // per wave: sums of the positive / negative
-                                // corrections still unknown (group g-1, own group)
+                                // corrections still unknown (groups g-1..g-LC, own group)
     // overlap bits per mover i, one 64-bit word over the partners j in which
     // wave w fills the slice of its own partners (bits w P .. w P + P - 1)
     static_assert(sizeof(SB) * M == 8, "the waves' slices tile a 64-bit word");
     alignas(8) SB ovo_own[kGroup][M];    // own group, j < i: overlap with j's old position
     alignas(8) SB ovt_own[kGroup][M];    //                   overlap with j's trial position
-    alignas(8) SB ovo_b[kGroup][M];      // group g-1: overlap with j's old / trial position
-    alignas(8) SB ovt_b[kGroup][M];
+    alignas(8) SB ovo_b[LC][kGroup][M];  // group g-1-kb: overlap with j's old / trial position
+    alignas(8) SB ovt_b[LC][kGroup][M];
     // corrections, one padded row per mover i (16-byte reads of 4 partners
     // are free of bank conflicts)
     static constexpr int CS = kGroup + (sizeof(T) == 4 ? 4 : 2);
     T c_own[kGroup][CS];           // own group [mover i][partner j]
-    T c_b[kGroup][CS];             // group g-1 [mover i][partner j]
+    T c_b[LC][kGroup][CS];         // group g-1-kb [mover i][partner j]
     T fac[kGroup];                 // chain wave: 0/1 factors of a row sum's mask
     int ready;                  // compute waves done filling the hand-off for the current target
     int consumed;               // local target index + 1 the chain wave last released
+    // the helper wave's part of the chain step: band corrections of groups
+    // g-LC..g-2 (summed oldest first), their overlap ballot, its factor row,
+    // and the local target index + 1 it last finished
+    double h_corr[LC > 1 ? kGroup : 1];
+    uint64_t h_ov;
+    T fac_h[LC > 1 ? kGroup : 1];
+    int h_done;
     // delayed acceptance: per mover, byte histograms of neighbour distances at
     // the old position (bytes 0..127) and at the trial position (128..255),
     // each like-charged bins 0..63 then unlike-charged; conflict ballots of
@@ -373,6 +386,34 @@ struct WgCounters {
     unsigned long long da_moves = 0, conflicts = 0, s1_rej = 0, s2_rej = 0, s1_pass = 0;
 };
 
+// The helper wave's part of the chain step of target g (wave 1, after its
+// own hand-off): once every wave's candidates are in, the band corrections
+// of groups g-LC..g-2 as their accept masks arrive, oldest first, for the
+// chain wave -- which meanwhile solves the own group's fixed point.
+template <typename T, int M, bool DA>
+__device__ __forceinline__ void band_helper(SweepShared<T, M, DA>& sh, __amdgpu_buffer_rsrc_t rec_r, int64_t g,
+                                            int t, int band, const Ctl& ctl) {
+    constexpr int LC = SweepShared<T, M, DA>::LC;
+    const int lane = threadIdx.x & 63;
+    wait_lds_at_least(&sh.ready, M, ctl);
+    double corr = 0.0;
+    bool ov = false;
+#pragma unroll
+    for (int kb = LC - 1; kb >= 1; --kb) {
+        if (kb < band) {
+            const GroupRec r = wait_rec(rec_r, g - 1 - kb, ctl);
+            corr += (double)masked_row_sum<T>(sh.c_b[kb][lane], sh.fac_h, r.acc);
+            const uint64_t ovo = slice_word(sh.ovo_b[kb][lane]), ovt = slice_word(sh.ovt_b[kb][lane]);
+            ov |= ((r.acc & ovt) | (~r.acc & ovo)) != 0;
+        }
+    }
+    sh.h_corr[lane] = corr;
+    const uint64_t ob = __ballot(ov);
+    if (lane == 0) sh.h_ov = ob;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) __hip_atomic_store(&sh.h_done, t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 #ifdef MC_TIMELINE
 constexpr int kTlSlots = 32;  // diagnostic build: stamps per group in the dE trace buffer
 #endif
@@ -404,7 +445,8 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
     tl1 = wall_clock64();
 #endif
     double St = 0.0;
-    uint64_t ovo = 0, ovt = 0, ovob = 0, ovtb = 0;
+    constexpr int LC = SweepShared<T, M, DA>::LC;
+    uint64_t ovo = 0, ovt = 0, ovob[LC], ovtb[LC];
     bool ovb = false;
     T cp = 0, cn = 0;
 #pragma unroll
@@ -416,8 +458,11 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
     }
     ovo = slice_word(sh.ovo_own[lane]);
     ovt = slice_word(sh.ovt_own[lane]);
-    ovob = slice_word(sh.ovo_b[lane]);
-    ovtb = slice_word(sh.ovt_b[lane]);
+#pragma unroll
+    for (int kb = 0; kb < LC; ++kb) {
+        ovob[kb] = slice_word(sh.ovo_b[kb][lane]);
+        ovtb[kb] = slice_word(sh.ovt_b[kb][lane]);
+    }
 
 #ifdef MC_TIMELINE
     tlA = wall_clock64();
@@ -473,7 +518,12 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
         const double e_hi = lq >= 0 ? lq * hi : lq * lo;
         const double span = (double)(cp - cn);
         const double margin = fabs(lq) * (1e-4 * span + 1e-9 * (fabs(St) + 1.0)) + 1e-12;
-        const uint64_t ov_sure = ovob & ovtb, ov_flip = (ovo ^ ovt) | (ovob ^ ovtb);
+        uint64_t ov_sure = 0, ov_flip = ovo ^ ovt;
+#pragma unroll
+        for (int kb = 0; kb < LC; ++kb) {
+            ov_sure |= ovob[kb] & ovtb[kb];
+            ov_flip |= ovob[kb] ^ ovtb[kb];
+        }
         const bool reject_sure = !can || s1_rej || ov_sure != 0 || (ovo & ovt) != 0;
         const bool accept_sure = !reject_sure && ov_flip == 0 && e_hi < thr_eff - margin;
         const bool sure = reject_sure || accept_sure || (ov_flip == 0 && e_lo >= thr_eff + margin);
@@ -515,33 +565,55 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
         acc = na;
         return own;
     };
-    double corr = 0.0;  // band correction of group g-1
+    double corr = 0.0;  // band corrections of groups g-LC..g-1, oldest first
 #ifdef MC_TIMELINE
     tlC = wall_clock64();
 #endif
+    // groups g-LC..g-2 come from the helper wave: their sum, in the same
+    // order, and the overlap ballot
+    auto helper_part = [&]() {
+        wait_lds_at_least(&sh.h_done, t + 1, ctl);
+        corr = sh.h_corr[lane];
+        ovb |= ((sh.h_ov >> lane) & 1ull) != 0;
+    };
     if (early) {
+        if (LC > 1 && band >= 2) helper_part();
         if (band >= 1) {
             const GroupRec r = wait_rec(rec_r, g - 1, ctl);
 #ifdef MC_TIMELINE
             tl2 = wall_clock64();
 #endif
-            corr += (double)masked_row_sum<T>(sh.c_b[lane], sh.fac, r.acc);
-            ovb |= ((r.acc & ovtb) | (~r.acc & ovob)) != 0;
+            corr += (double)masked_row_sum<T>(sh.c_b[0][lane], sh.fac, r.acc);
+            ovb |= ((r.acc & ovtb[0]) | (~r.acc & ovob[0])) != 0;
         }
         // exact energy change of the (already decided) trials
         const T own = acc ? masked_row_sum<T>(sh.c_own[lane], sh.fac, acc) : (T)0;
         dE = lq * ((St + corr) + (double)own);
         it = 1;
     } else {
-        // While group g-1's accept mask is on its way, the fixed point is
-        // solved for a guess of it (every move of g-1 rejected); once the
-        // mask is in, one evaluation with the true band correction confirms
-        // the guessed solution, or the iteration goes on from it.
-        T own = 0;
+        // While the accept masks of the chain band groups are on their way,
+        // the fixed point is solved for a guess of them (every move
+        // rejected).  As the true corrections come in (the helper's, then
+        // g-1's) one evaluation confirms the solution, or the iteration goes
+        // on from it.
+        uint64_t pend = 0;  // overlaps with old positions of pending groups (rejected guess)
+#pragma unroll
+        for (int kb = 0; kb < LC; ++kb)
+            if (kb < band) pend |= ovob[kb];
+        T own = solve(St, valid && !wall && !ovb && pend == 0, 0, (T)0);
+        if (LC > 1 && band >= 2) {
+#ifdef MC_TIMELINE
+            tlC = wall_clock64();  // end of the first solve
+#endif
+            helper_part();
+#ifdef MC_TIMELINE
+            tlB = wall_clock64();  // helper's part in
+#endif
+            pend = ovob[0];
+            it = 0;
+            own = solve(St + corr, valid && !wall && !ovb && pend == 0, acc, own);
+        }
         if (band >= 1) {
-            const bool can_g = valid && !wall && !ovb && ovob == 0;
-            own = solve(St + corr, can_g, 0, (T)0);
-            const uint64_t guess = acc;
 #ifdef MC_TIMELINE
             tl6 = wall_clock64();
 #endif
@@ -549,24 +621,19 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
 #ifdef MC_TIMELINE
             tl2 = wall_clock64();
 #endif
-            corr += (double)masked_row_sum<T>(sh.c_b[lane], sh.fac, r.acc);
-            ovb |= ((r.acc & ovtb) | (~r.acc & ovob)) != 0;
+            corr += (double)masked_row_sum<T>(sh.c_b[0][lane], sh.fac, r.acc);
+            ovb |= ((r.acc & ovtb[0]) | (~r.acc & ovob[0])) != 0;
 #ifdef MC_TIMELINE
             tl4 = wall_clock64();
 #endif
-            St += corr;
             it = 0;
-            own = solve(St, valid && !wall && !ovb, guess, own);
-        } else {
-#ifdef MC_TIMELINE
-            tl2 = tl4 = wall_clock64();
-#endif
-            St += corr;
-            own = solve(St, valid && !wall && !ovb, 0, (T)0);
+            own = solve(St + corr, valid && !wall && !ovb, acc, own);
         }
 #ifdef MC_TIMELINE
+        if (band < 1) tl2 = tl4 = tl6 = wall_clock64();
         tl5 = wall_clock64();
 #endif
+        (void)own;
         publish_group<T>(rec_r, pos_r, g, s, npad, ion, acc, dec, xi, yi, zi, txi, tyi, tzi);
 #ifdef MC_TIMELINE
         tl3 = wall_clock64();
@@ -845,6 +912,7 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
     using IO = PosIO<T>;
     constexpr int P = kGroup / M;
     constexpr int KB = SweepShared<T, M, DA>::KB;
+    constexpr int LC = SweepShared<T, M, DA>::LC;
     using SB = typename SliceBits<P>::type;
     __shared__ SweepShared<T, M, DA> sh;
 
@@ -869,6 +937,7 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
     if (threadIdx.x == 0) {
         sh.ready = 0;
         sh.consumed = 0;
+        sh.h_done = 0;
         if (k_wg == 0) cd.clk[0] = wall_clock64();
     }
     if constexpr (DA) {
@@ -1047,13 +1116,19 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
             auto hand_off_candidates = [&]() {
                 sh.ovo_own[lane][wave] = ovo_own;
                 sh.ovt_own[lane][wave] = ovt_own;
-                sh.ovo_b[lane][wave] = ovo_band[0];
-                sh.ovt_b[lane][wave] = ovt_band[0];
+#pragma unroll
+                for (int kb = 0; kb < LC; ++kb) {
+                    sh.ovo_b[kb][lane][wave] = ovo_band[kb];
+                    sh.ovt_b[kb][lane][wave] = ovt_band[kb];
+                }
                 T cp = 0, cn = 0;
 #pragma unroll
                 for (int m = 0; m < P; ++m) {
-                    cp += c_band[0][m] > 0 ? c_band[0][m] : (T)0;
-                    cn += c_band[0][m] < 0 ? c_band[0][m] : (T)0;
+#pragma unroll
+                    for (int kb = 0; kb < LC; ++kb) {
+                        cp += c_band[kb][m] > 0 ? c_band[kb][m] : (T)0;
+                        cn += c_band[kb][m] < 0 ? c_band[kb][m] : (T)0;
+                    }
                     cp += c_own[m] > 0 ? c_own[m] : (T)0;
                     cn += c_own[m] < 0 ? c_own[m] : (T)0;
                 }
@@ -1062,7 +1137,9 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
 #pragma unroll
                 for (int m = 0; m < P; ++m) {
                     sh.c_own[lane][wave * P + m] = c_own[m];
-                    sh.c_b[lane][wave * P + m] = c_band[0][m];  // zero when band = 0
+#pragma unroll
+                    for (int kb = 0; kb < LC; ++kb)
+                        sh.c_b[kb][lane][wave * P + m] = c_band[kb][m];  // zero beyond the band
                 }
             };
             if constexpr (!DA) {
@@ -1168,10 +1245,10 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
             // this wave's slice of their candidates becomes final
             GroupRec rb[KB];
 #pragma unroll
-            for (int kb = 1; kb < KB; ++kb)  // all loads in flight at once
+            for (int kb = LC; kb < KB; ++kb)  // all loads in flight at once
                 if (kb < band) rb[kb] = load_rec(rec_r, (uint32_t)((g - 1 - kb) & (kRing - 1)));
 #pragma unroll
-            for (int kb = KB - 1; kb >= 1; --kb) {
+            for (int kb = KB - 1; kb >= LC; --kb) {
                 if (kb < band) {
                     const GroupRec r = rb[kb].tag == (uint32_t)(g - kb) ? rb[kb] : wait_rec(rec_r, g - 1 - kb, ctl);
                     const uint32_t a = (uint32_t)(r.acc >> (wave * P));
@@ -1213,7 +1290,17 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
                 ((uint64_t*)cd.trace_de)[kTlSlots * g + 16 + wave] = wall_clock64();
 #endif
 
-            // ---- wave 0 finishes the group: decisions and publication
+            // ---- wave 1 helps with the older chain band groups, wave 0
+            // finishes the group: decisions and publication
+            if constexpr (LC > 1) {
+                if (wave == 1 && band >= 2) {
+                    band_helper<T, M, DA>(sh, rec_r, g, t, band, ctl);
+#ifdef MC_TIMELINE
+                    if (lane == 0 && kTlSlots * (g + 1) <= cd.trace_cap)
+                        ((uint64_t*)cd.trace_de)[kTlSlots * g + 28] = wall_clock64();
+#endif
+                }
+            }
             if (wave == 0) {
                 chain_step<T, M, DA>(sh, cd, pos_r, rec_r, g_begin, g, t, xi, yi, zi, txi, tyi, tzi, mi, da_on,
                                      ctl, ctr);
