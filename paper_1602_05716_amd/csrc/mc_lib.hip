@@ -40,8 +40,14 @@ enum { ST_MOVES = 0, ST_ACC, ST_WALL, ST_OVERLAP, ST_METRO, ST_ITERS, ST_EARLY,
 constexpr int64_t kMaxLaunchSweeps = 4096;
 static_assert(kDaParams == MC_DA_NPARAM, "network size differs from the header");
 // Default cost model of a chain (microseconds): per-sweep time
-// t(nb, w) = a nb + b nb^2 / w for nb groups of 64 served by w workgroups.
-constexpr double kModelA = 2.5, kModelB = 0.7;
+// t(nb, w) = a nb + b nb^2 / w for nb groups of 64 served by w workgroups
+// (a: one group's decision step; b: one 64 x 64 partner tile of a workgroup
+// sharing its CU).  The autotuner keeps a within [kModelAMin, kModelAMax]:
+// per-chain times from one shared launch cannot always tell the two terms
+// apart, and a latency term far outside what a group's step costs misleads
+// the schedule.
+constexpr double kModelA = 1.2, kModelB = 1.3;
+constexpr double kModelAMin = 0.3, kModelAMax = 4.0;
 
 struct DeviceInfo {
     int device = -1;
@@ -1324,6 +1330,12 @@ int mc_autotune(mc_handle* h, int32_t calib_sweeps, uint64_t seed, double* model
     if (used >= 2 && det > 1e-12 * s11 * s22) {
         a = (r1 * s22 - r2 * s12) / det;
         b = (s11 * r2 - s12 * r1) / det;
+    }
+    if (used >= 1 && s22 > 0 && !(a >= kModelAMin && a <= kModelAMax)) {
+        // latency term out of range: hold it at the bound (or the default)
+        // and refit the work term alone
+        a = (a > kModelAMax) ? kModelAMax : (a < kModelAMin ? kModelAMin : kModelA);
+        b = (r2 - a * s12) / s22;
     }
     if (!(a > 0) || !(b > 0)) {
         // degenerate fit (e.g. one chain): one-parameter fits, keeping the model's ratio
