@@ -329,10 +329,11 @@ int mc_autotune(mc_handle* h, int32_t calib_sweeps, uint64_t seed, double* model
  * bfloat16 weights, float sums, hidden activations rounded to bfloat16.
  * Conflict rule: a move whose old or trial position lies within rcut of the
  * old or trial position of an ion whose decision is still pending (the
- * previous 64-ion group of the chain's sequence of groups, or a lower ion of
- * its own group) takes the plain test; the rule depends on the unordered
- * pair {x_i, x~_i} only, so detailed balance holds move by move.
- * Surrogate chains use one band group (band 1).
+ * previous `band` 64-ion groups of the chain's sequence of groups, or a lower
+ * ion of its own group) takes the plain test; the rule depends on the
+ * unordered pair {x_i, x~_i} only, so detailed balance holds move by move.
+ * A wider band makes more moves take the plain test and takes the network
+ * off the decision chain's critical path.
  * ------------------------------------------------------------------------ */
 
 /* Number of network parameters: W1 [128 x 128] (row = input), b1 [128],

@@ -851,9 +851,9 @@ int create_handle(int32_t n_chains, const mc_chain_spec* specs, const mc_options
         }
     }
     if (opt.log_moves > 0) {
-        // logging runs the delayed-acceptance kernel (features), with its band of one group
+        // logging runs the delayed-acceptance kernel (features)
         h->da_kernel = true;
-        for (Chain& c : h->chains) c.band = std::min(c.band, 1);
+        for (Chain& c : h->chains) c.band = std::min(c.band, kDaMaxBand);
     }
     std::vector<int> wg;
     std::vector<int2> map;
@@ -1418,7 +1418,7 @@ int mc_set_surrogate(mc_handle* h, int32_t chain, const double* params, double r
         ds.last_rate = -1.0;
         ds.min_count = 64;
         HIPCHECK(h, hipMemcpy(c.da, &ds, sizeof(ds), hipMemcpyHostToDevice));
-        c.band = std::min(c.band, 1);
+        c.band = std::min(c.band, kDaMaxBand);
     }
     h->da_window = h->opt.da_window;
     if (!h->da_kernel) {

@@ -206,15 +206,16 @@ template <int P> struct SliceBits;
 template <> struct SliceBits<8> { using type = uint8_t; };
 template <> struct SliceBits<16> { using type = uint16_t; };
 
-// Band groups with both-outcome candidates: kMaxBand, or 1 for the
-// delayed-acceptance kernels (whose LDS also holds neighbour histograms).
+// Band groups with both-outcome candidates: up to kMaxBand (kDaMaxBand in
+// the delayed-acceptance kernels, whose network would otherwise spill).
 // The newest kChainSlots of them (g-1, g-2[, g-3]) go to the chain step
 // through LDS; the accept masks of the older ones are out before the compute
 // waves finish, and each wave resolves its own slice of their candidates
 // itself.  (The float kernels keep two slots: a third would no longer let
 // two workgroups share a CU's LDS.  The double kernels run one workgroup
-// per CU and take three.)
-template <bool DA> constexpr int kBandSlots = DA ? 1 : kMaxBand;
+// per CU and take three.  The delayed-acceptance kernels, whose LDS also
+// holds the neighbour histograms and the network, take one.)
+template <bool DA> constexpr int kBandSlots = DA ? kDaMaxBand : kMaxBand;
 template <typename T, int M, bool DA>
 constexpr int kChainSlots = DA ? 1 : (sizeof(T) == 4 ? 2 : 3);
 // A compute wave waiting for a partner group more than this many groups
@@ -1240,9 +1241,19 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
                 ((uint64_t*)cd.trace_de)[kTlSlots * g + 12] = wall_clock64();
 #endif
 
-            // ---- band groups older than g-1: their accept masks are out by
-            // now (published about one group after the last partner tile);
-            // this wave's slice of their candidates becomes final
+            // ---- delayed acceptance: the features are complete after the
+            // last partner tile, so the network runs here, while the older
+            // band groups' accept masks are still on their way
+            if constexpr (DA) {
+                wait_lds_at_least(&sh.consumed, t, ctl);
+                const uint64_t cb = __ballot(conf);
+                if (lane == 0) sh.part_conf[wave] = cb;
+                da_network<T, M>(sh, cd, wave, lane, da_on, s * (int64_t)cd.n + ion, ion < cd.n, g);
+            }
+
+            // ---- band groups older than the chain step's: their accept
+            // masks are out by now (published about one group after the last
+            // partner tile); this wave's slice of their candidates becomes final
             GroupRec rb[KB];
 #pragma unroll
             for (int kb = LC; kb < KB; ++kb)  // all loads in flight at once
@@ -1270,12 +1281,6 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
                 ((uint64_t*)cd.trace_de)[kTlSlots * g + (wave == 0 ? 13 : 20 + wave)] = wall_clock64();
 #endif
             // ---- hand off to the chain wave once it has released the previous target
-            if constexpr (DA) {
-                wait_lds_at_least(&sh.consumed, t, ctl);
-                const uint64_t cb = __ballot(conf);
-                if (lane == 0) sh.part_conf[wave] = cb;
-                da_network<T, M>(sh, cd, wave, lane, da_on, s * (int64_t)cd.n + ion, ion < cd.n, g);
-            }
             if constexpr (DA) hand_off_candidates();
             sh.part_s[wave][lane] = S;
             {

@@ -37,12 +37,12 @@ def _feat_ints(f8):
     return f8.astype(np.int32)
 
 
-def _check_da(oracle, sy, precision, sweeps, seed, D, params, da_on=True, tol_de=None, rc=4.0):
+def _check_da(oracle, sy, precision, sweeps, seed, D, params, da_on=True, tol_de=None, rc=4.0, band=1):
     from paper_1602_05716_amd import mc
     n_moves = sweeps * sy.n
-    _say("da %s N=%d sweeps=%d seed=%d da_on=%s rc=%g" % (precision, sy.n, sweeps, seed, da_on, rc))
+    _say("da %s N=%d sweeps=%d seed=%d da_on=%s rc=%g band=%d" % (precision, sy.n, sweeps, seed, da_on, rc, band))
     with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision=precision, max_disp=0.5 * D,
-                  trace_moves=n_moves, log_moves=n_moves, resum_every=0, waves=4, da_rcut=rc) as ch:
+                  trace_moves=n_moves, log_moves=n_moves, resum_every=0, waves=4, da_rcut=rc, band=band) as ch:
         if da_on:
             ch.set_surrogate(params, -1.0, True)
         ch.sweep(sweeps, seed)
@@ -115,6 +115,29 @@ def test_da_fp32_two_stage_parity(oracle):
     assert st["da_active"] == 1 and st["da_stage1_rejected"] > 200
 
 
+def test_da_fp32_band3_parity(oracle):
+    """Float path with the delayed-acceptance kernel's widest band: three
+    pending groups in the conflict rule, the older two resolved from their
+    accept masks by the compute waves, the network run before those masks
+    arrive.  rc = 2 leaves more than a quarter of the moves to the two-stage
+    test at N = 4096."""
+    sy = _sys(4096, 0.05, 0.7, seed=45)
+    p = _params(10, 0.2)
+    st, r, lg = _check_da(oracle, sy, "fp32", 2, 0xDA33, 3.0, p, tol_de=TOL32, rc=2.0, band=3)
+    assert st["band"] == 3 and st["da_active"] == 1
+    n_moves = 2 * sy.n
+    assert st["da_moves"] + st["da_conflicts"] == n_moves and st["da_moves"] > n_moves // 4
+    assert st["da_stage1_rejected"] > 200
+
+
+def test_da_fp64_band2_parity(oracle):
+    """Double path, band 2 (one group resolved by the compute waves)."""
+    sy = _sys(2048, 0.05, 0.8, seed=46)
+    p = _params(11, 0.2)
+    st, r, lg = _check_da(oracle, sy, "fp64", 2, 0xDA62, 2.0, p, rc=2.0, band=2)
+    assert st["band"] == 2 and st["da_active"] == 1 and st["da_moves"] > 2 * sy.n // 4
+
+
 def test_plain_mode_logging_matches_oracle(oracle):
     """Logging without a surrogate: plain decisions (bit-exact in double),
     exact histograms and conflict flags for every logged move."""
@@ -134,7 +157,8 @@ def test_drift_monitor_falls_back(oracle):
     D, seed, sweeps = 2.0, 0xFA11, 4
     n_moves = sweeps * sy.n
     with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision="fp64", max_disp=0.5 * D,
-                  trace_moves=n_moves, resum_every=0, waves=4, da_window=2, da_delta=0.0, da_rcut=1.5) as ch:
+                  trace_moves=n_moves, resum_every=0, waves=4, da_window=2, da_delta=0.0, da_rcut=1.5,
+                  band=1) as ch:
         ch.set_surrogate(p, 0.0, True)
         ch.sweep(sweeps, seed)
         acc, de = ch.trace(n_moves)
