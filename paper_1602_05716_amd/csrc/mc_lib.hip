@@ -76,7 +76,7 @@ bool device_info(DeviceInfo& di, std::string& err) {
     return true;
 }
 
-using SweepFn = void (*)(const ChainDesc*, const int2*, uint32_t, int32_t, Ctl);
+using SweepFn = void (*)(const ChainDesc*, const int2*, const int2*, uint32_t, int32_t, Ctl);
 
 template <typename T, int M, bool U, bool DA = false>
 SweepFn sweep_fn() {
@@ -107,6 +107,10 @@ struct Chain {
     double sigma0 = 1.0;
     uint32_t chain_id = 0;
     int band = 0;
+    // the cost model's factor for this chain: its measured time in the last
+    // calibration over the model's prediction (1 until measured)
+    double cost_scale = 1.0;
+    bool measured = false;
     int wg = 1;
     std::vector<std::pair<double, double>> species;  // (charge, diameter)
     std::vector<int64_t> n_of_type;
@@ -171,7 +175,8 @@ struct mc_handle {
     void* arena = nullptr;
     int* abort_flag = nullptr;
     ChainDesc* d_desc = nullptr;
-    int2* d_wgmap = nullptr;
+    int2* d_wgmap = nullptr;      // [cap + chains] items (chain, index among the chain's workgroups)
+    int2* d_wgrange = nullptr;    // [cap] per workgroup: its items [begin, end)
     BlockItem* d_eitems = nullptr;   // energy re-sum blocks
     int n_eitems = 0;
     BlockItem* d_ritems = nullptr;   // g(r) blocks
@@ -389,44 +394,102 @@ struct ArenaPlan {
 };
 
 double chain_cost(const mc_handle* h, const Chain& c, int w) {
-    return h->model_a * c.nb + h->model_b * (double)c.nb * c.nb / std::max(1, w);
+    return c.cost_scale * (h->model_a * c.nb + h->model_b * (double)c.nb * c.nb / std::max(1, w));
 }
 
-// Workgroups per chain: water filling of the budget on the cost model
-// (each step gives one more workgroup to the chain that would finish last),
-// then the grid order: chains' workgroups sorted by per-workgroup work, the
-// heaviest half placed in order and the lightest half after it in reverse,
-// so that grid positions i and i + W/2 pair heavy with light.
-void plan_schedule(mc_handle* h, std::vector<int>& wg, std::vector<int2>& map) {
+// A workgroup's items: (chain, index of the workgroup among the chain's).
+using WgLists = std::vector<std::vector<int2>>;
+
+// Grid order: workgroups sorted by their work (sum of nb^2 / w over their
+// items), the heaviest half placed in order and the lightest half after it
+// in reverse, so that grid positions i and i + W/2 pair heavy with light.
+void order_grid(std::vector<std::pair<double, std::vector<int2>>>& per, WgLists& lists) {
+    std::stable_sort(per.begin(), per.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    const int W = (int)per.size(), half = (W + 1) / 2;
+    lists.assign(W, {});
+    for (int q = 0; q < W; ++q) lists[q < half ? q : W - 1 - (q - half)] = std::move(per[q].second);
+}
+// Workgroups per chain and the grid, on the cost model, for a target sweep
+// time T.  A chain whose cost was measured (autotuner) and that one
+// workgroup brings within T shares a workgroup with others: first fit by
+// decreasing time, the workgroup running them one after another.  Every
+// other chain gets the fewest workgroups that bring it within T (at most one
+// per group).  T is the smallest value (bisection) whose plan fits the
+// budget; workgroups left over go, one at a time, to the multi-workgroup
+// chain predicted to finish last.
+void plan_schedule(mc_handle* h, std::vector<int>& wg, WgLists& lists) {
     const int nc = (int)h->chains.size();
-    wg.assign(nc, 1);
-    int used = nc;
+    const int budget = h->da_kernel ? std::min(h->wg_budget, h->cap_da) : h->wg_budget;
+    std::vector<int> order(nc);
+    for (int k = 0; k < nc; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return chain_cost(h, h->chains[x], 1) > chain_cost(h, h->chains[y], 1);
+    });
+    std::vector<double> bin_t;
+    std::vector<std::vector<int2>> bin_items;
+    auto plan = [&](double T, std::vector<int>& w) {
+        w.assign(nc, 0);
+        bin_t.clear();
+        bin_items.clear();
+        int used = 0;
+        for (int k : order) {
+            const Chain& c = h->chains[k];
+            const double t1 = chain_cost(h, c, 1);
+            if (t1 > T || !c.measured) {
+                int need = c.nb;
+                for (int ww = 1; ww <= c.nb; ++ww)
+                    if (chain_cost(h, c, ww) <= T) { need = ww; break; }
+                w[k] = need;
+                used += need;
+            } else {
+                size_t q = 0;
+                while (q < bin_t.size() && bin_t[q] + t1 > T) ++q;
+                if (q == bin_t.size()) {
+                    bin_t.push_back(0.0);
+                    bin_items.emplace_back();
+                }
+                bin_t[q] += t1;
+                bin_items[q].push_back(make_int2(k, 0));
+                w[k] = 1;
+            }
+        }
+        return used + (int)bin_t.size();
+    };
+    double lo = 0.0, hi = 0.0;
+    for (int k = 0; k < nc; ++k) hi = std::max(hi, chain_cost(h, h->chains[k], 1));
+    for (int it = 0; it < 50; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        std::vector<int> w;
+        if (plan(mid, w) <= budget) hi = mid; else lo = mid;
+    }
+    int used = plan(hi, wg);
+    std::vector<char> packed(nc, 0);
+    for (const auto& b : bin_items)
+        for (const int2& it : b) packed[it.x] = 1;
     using Item = std::pair<double, int>;
     std::priority_queue<Item> pq;
-    for (int k = 0; k < nc; ++k) pq.emplace(chain_cost(h, h->chains[k], 1), k);
-    const int budget = h->da_kernel ? std::min(h->wg_budget, h->cap_da) : h->wg_budget;
-    while (!pq.empty() && used < budget) {
+    for (int k = 0; k < nc; ++k)
+        if (!packed[k] && wg[k] < h->chains[k].nb) pq.emplace(chain_cost(h, h->chains[k], wg[k]), k);
+    while (used < budget && !pq.empty()) {
         const int k = pq.top().second;
         pq.pop();
-        const Chain& c = h->chains[k];
-        if (wg[k] >= c.nb) continue;  // cannot use more workgroups than groups
         wg[k] += 1;
         used += 1;
-        pq.emplace(chain_cost(h, c, wg[k]), k);
+        if (wg[k] < h->chains[k].nb) pq.emplace(chain_cost(h, h->chains[k], wg[k]), k);
     }
-    std::vector<std::pair<double, int2>> per;  // (work per workgroup, (chain, index))
+    std::vector<std::pair<double, std::vector<int2>>> per;
     for (int k = 0; k < nc; ++k) {
-        const Chain& c = h->chains[k];
-        const double work = (double)c.nb * c.nb / wg[k];
-        for (int j = 0; j < wg[k]; ++j) per.emplace_back(work, make_int2(k, j));
+        if (packed[k]) continue;
+        const double work = (double)h->chains[k].nb * h->chains[k].nb / wg[k];
+        for (int j = 0; j < wg[k]; ++j) per.emplace_back(work, std::vector<int2>{make_int2(k, j)});
     }
-    std::stable_sort(per.begin(), per.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-    const int W = (int)per.size();
-    map.assign(W, make_int2(0, 0));
-    const int half = (W + 1) / 2;
-    for (int q = 0; q < W; ++q) map[q < half ? q : W - 1 - (q - half)] = per[q].second;
+    for (size_t q = 0; q < bin_items.size(); ++q) {
+        double work = 0.0;
+        for (const int2& it : bin_items[q]) work += (double)h->chains[it.x].nb * h->chains[it.x].nb;
+        per.emplace_back(work, bin_items[q]);
+    }
+    order_grid(per, lists);
 }
-
 // Fills every chain's descriptor from the host state.
 void fill_desc(mc_handle* h) {
     for (Chain& c : h->chains) {
@@ -488,11 +551,19 @@ int upload_desc(mc_handle* h) {
 }
 
 // Applies a workgroup count per chain: new grid map and descriptors.
-int apply_schedule(mc_handle* h, const std::vector<int>& wg, const std::vector<int2>& map) {
+int apply_schedule(mc_handle* h, const std::vector<int>& wg, const WgLists& lists) {
+    std::vector<int2> items, range;
+    for (const auto& l : lists) {
+        range.push_back(make_int2((int)items.size(), (int)(items.size() + l.size())));
+        items.insert(items.end(), l.begin(), l.end());
+    }
+    if (range.empty() || (int)range.size() > h->cap || items.size() > (size_t)h->cap + h->chains.size())
+        return fail(h, MC_E_STATE, "schedule does not fit the launch");
     for (size_t k = 0; k < h->chains.size(); ++k) h->chains[k].wg = wg[k];
-    h->wg_total = (int)map.size();
+    h->wg_total = (int)range.size();
     HIPCHECK(h, hipStreamSynchronize(h->stream));
-    HIPCHECK(h, hipMemcpy(h->d_wgmap, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMemcpy(h->d_wgmap, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMemcpy(h->d_wgrange, range.data(), sizeof(int2) * range.size(), hipMemcpyHostToDevice));
     return upload_desc(h);
 }
 
@@ -572,8 +643,9 @@ int launch_sweeps(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
     uint32_t s0 = (uint32_t)h->sweeps;
     int32_t ns = (int32_t)n_sweeps;
     const ChainDesc* dd = h->d_desc;
+    const int2* wr = h->d_wgrange;
     const int2* wm = h->d_wgmap;
-    void* args[] = {(void*)&dd, (void*)&wm, (void*)&s0, (void*)&ns, (void*)&ctl};
+    void* args[] = {(void*)&dd, (void*)&wr, (void*)&wm, (void*)&s0, (void*)&ns, (void*)&ctl};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->opt.record_timing) {
         HIPCHECK(h, hipEventCreate(&e0));
@@ -698,7 +770,8 @@ int create_handle(int32_t n_chains, const mc_chain_spec* specs, const mc_options
     ArenaPlan plan;
     plan.add(&h->abort_flag, sizeof(int));
     plan.add(&h->d_desc, sizeof(ChainDesc) * n_chains);
-    plan.add(&h->d_wgmap, sizeof(int2) * h->cap);
+    plan.add(&h->d_wgmap, sizeof(int2) * (h->cap + n_chains));
+    plan.add(&h->d_wgrange, sizeof(int2) * h->cap);
     int n_e = 0, n_r = 0;
     size_t max_hist = 0;
     for (Chain& c : h->chains) {
@@ -856,9 +929,9 @@ int create_handle(int32_t n_chains, const mc_chain_spec* specs, const mc_options
         for (Chain& c : h->chains) c.band = std::min(c.band, kDaMaxBand);
     }
     std::vector<int> wg;
-    std::vector<int2> map;
-    plan_schedule(h, wg, map);
-    if ((rc = apply_schedule(h, wg, map))) return bail(rc);
+    WgLists lists;
+    plan_schedule(h, wg, lists);
+    if ((rc = apply_schedule(h, wg, lists))) return bail(rc);
     // initial energy: re-sum into the running energy
     if ((rc = launch_energy(h, 1, 0))) return bail(rc);
     if ((rc = sync_check(h))) return bail(rc);
@@ -1280,15 +1353,13 @@ int mc_set_schedule(mc_handle* h, const int32_t* workgroups) {
     int rc = sync_check(h);
     if (rc) return rc;
     std::vector<int> wg(workgroups, workgroups + h->chains.size());
-    std::vector<std::pair<double, int2>> per;
+    std::vector<std::pair<double, std::vector<int2>>> per;
     for (size_t k = 0; k < h->chains.size(); ++k)
         for (int j = 0; j < wg[k]; ++j)
-            per.emplace_back((double)h->chains[k].nb * h->chains[k].nb / wg[k], make_int2((int)k, j));
-    std::stable_sort(per.begin(), per.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-    const int W = (int)per.size(), half = (W + 1) / 2;
-    std::vector<int2> map(W);
-    for (int q = 0; q < W; ++q) map[q < half ? q : W - 1 - (q - half)] = per[q].second;
-    return apply_schedule(h, wg, map);
+            per.emplace_back((double)h->chains[k].nb * h->chains[k].nb / wg[k], std::vector<int2>{make_int2((int)k, j)});
+    WgLists lists;
+    order_grid(per, lists);
+    return apply_schedule(h, wg, lists);
 }
 
 int mc_chain_launch_ms(mc_handle* h, double* ms) {
@@ -1354,14 +1425,26 @@ int mc_autotune(mc_handle* h, int32_t calib_sweeps, uint64_t seed, double* model
     }
     h->model_a = a;
     h->model_b = b;
+    // per-chain factors: what the two-term model misses for one chain
+    // (sharing a CU, short chains' fixed costs) it measured here
+    for (size_t k = 0; k < h->chains.size(); ++k) {
+        Chain& c = h->chains[k];
+        const double t = 1e3 * ms[k] / calib_sweeps;
+        c.cost_scale = 1.0;
+        const double pred = a * c.nb + b * (double)c.nb * c.nb / c.wg;
+        if (t > 0 && pred > 0) {
+            c.cost_scale = std::min(4.0, std::max(0.25, t / pred));
+            c.measured = true;
+        }
+    }
     if (model) {
         model[0] = a;
         model[1] = b;
     }
     std::vector<int> wg;
-    std::vector<int2> map;
-    plan_schedule(h, wg, map);
-    if ((rc = apply_schedule(h, wg, map))) return rc;
+    WgLists lists;
+    plan_schedule(h, wg, lists);
+    if ((rc = apply_schedule(h, wg, lists))) return rc;
     if (h->opt.resum_every > 0 && h->sweeps % h->opt.resum_every == 0 && (rc = launch_energy(h, 1, 1))) return rc;
     return MC_OK;
 }
@@ -1426,9 +1509,9 @@ int mc_set_surrogate(mc_handle* h, int32_t chain, const double* params, double r
             return fail(h, MC_E_ARG, "more chains than co-resident workgroups of the delayed-acceptance kernel");
         h->da_kernel = true;
         std::vector<int> wg;
-        std::vector<int2> map;
-        plan_schedule(h, wg, map);
-        return apply_schedule(h, wg, map);
+        WgLists lists;
+        plan_schedule(h, wg, lists);
+        return apply_schedule(h, wg, lists);
     }
     return upload_desc(h);
 }

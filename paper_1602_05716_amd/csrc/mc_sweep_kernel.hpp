@@ -903,11 +903,11 @@ __device__ __forceinline__ void da_network(SweepShared<T, M, true>& sh, const Ch
     }
 }
 
-template <typename T, int M, bool UNIFORM_SIGMA, bool DA = false>
-__global__ void __launch_bounds__(64 * M)
-__attribute__((amdgpu_waves_per_eu(kWavesPerEU<T, M, DA>)))
-sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_map,
-             uint32_t s0, int32_t n_sweeps, Ctl ctl)
+// One workgroup's share of one chain for sweeps s0 .. s0 + n_sweeps - 1:
+// the targets g = k_wg (mod the chain's workgroup count).
+template <typename T, int M, bool UNIFORM_SIGMA, bool DA>
+__device__ __forceinline__ void sweep_chain(SweepShared<T, M, DA>& sh, const ChainDesc& cd, const int k_wg,
+                                            uint32_t s0, int32_t n_sweeps, const Ctl& ctl)
 {
     using T4 = typename Prec<T>::T4;
     using IO = PosIO<T>;
@@ -915,14 +915,9 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
     constexpr int KB = SweepShared<T, M, DA>::KB;
     constexpr int LC = SweepShared<T, M, DA>::LC;
     using SB = typename SliceBits<P>::type;
-    __shared__ SweepShared<T, M, DA> sh;
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // workgroup -> (chain, index of the workgroup among the chain's)
-    const int2 wm = wg_map[blockIdx.x];
-    const ChainDesc& cd = chains[wm.x];
-    const int k_wg = wm.y;
 
     const int nb = cd.nb, band = cd.band;
     const int npad = nb * kGroup;
@@ -1328,6 +1323,25 @@ sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_m
             atomicAdd(&cd.stats[10], ctr.s1_pass);
             atomicAdd(&cd.stats[11], ctr.s2_rej);
         }
+    }
+    __syncthreads();  // every wave is done with this chain's LDS state
+}
+
+// The sweep launch.  Workgroup w runs its items (chain, index of the
+// workgroup among the chain's) one after another: a chain served by several
+// workgroups is their only item; chains served by one workgroup alone may
+// share it (a chain never waits on a workgroup busy with another chain).
+template <typename T, int M, bool UNIFORM_SIGMA, bool DA = false>
+__global__ void __launch_bounds__(64 * M)
+__attribute__((amdgpu_waves_per_eu(kWavesPerEU<T, M, DA>)))
+sweep_kernel(const ChainDesc* __restrict__ chains, const int2* __restrict__ wg_range,
+             const int2* __restrict__ items, uint32_t s0, int32_t n_sweeps, Ctl ctl)
+{
+    __shared__ SweepShared<T, M, DA> sh;
+    const int2 r = wg_range[blockIdx.x];
+    for (int q = r.x; q < r.y; ++q) {
+        const int2 it = items[q];
+        sweep_chain<T, M, UNIFORM_SIGMA, DA>(sh, chains[it.x], it.y, s0, n_sweeps, ctl);
     }
 }
 
