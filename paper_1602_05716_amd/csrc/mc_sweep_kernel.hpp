@@ -21,18 +21,24 @@
 //     stream order, as they get decided (the upper/lower triangle split of
 //     Sec. 2 applied continuously across sweep boundaries).
 //   * For the last `band` groups and for the mover's own group, both possible
-//     outcomes of partner j are evaluated ahead of time (old position and
-//     trial position), so that once j's accept bit is known only a select and
-//     an add remain on the critical path.
-//   * The waves hand their partial sums and candidate corrections over
-//     through LDS and move on to their next target; they never wait for an
-//     accept mask.  Wave 0 then decides the group: if the threshold lies
-//     outside the interval spanned by the unknown corrections for every
-//     lane, at once; otherwise it waits for the band groups' accept masks
-//     and finds the group's own accept bits by iterating the sequential rule
-//     a_i = f_i(a_0..a_{i-1}) to its fixed point (Jacobi sweeps over the
-//     wave; the fixed point is unique, equals the sequential outcome and is
-//     reached in at most 64 iterations, usually two).
+//     outcomes of partner j are evaluated at the start of the target's work
+//     (old position and trial position), so that once j's accept bit is
+//     known only a select and an add remain.
+//   * The newest band groups' candidates (g-1, g-2) and the own group's go to
+//     LDS for the chain step as soon as they are computed.  The older band
+//     groups' accept masks are published before the compute waves finish;
+//     each wave folds its slice of their candidates from the mask, then hands
+//     over its partial sum and moves on to its next target.
+//   * Wave 0 then decides the group: if the threshold lies outside the
+//     interval spanned by the unknown corrections for every lane, at once.
+//     Otherwise it solves the group's own accept bits, the fixed point of the
+//     sequential rule a_i = f_i(a_0..a_{i-1}) (Jacobi sweeps over the wave;
+//     the system is lower triangular, so the fixed point is unique, equals
+//     the sequential outcome and is reached from any start), for a guess of
+//     the pending band groups' masks (all rejected), while wave 1 sums the
+//     older pending groups' masked rows as their masks arrive.  Each true
+//     correction then costs one evaluation when the guess was right, a few
+//     more iterations when not.
 //   * Publication: the accept mask goes out at once in the group record; the
 //     new positions are written in place, double buffered by sweep parity,
 //     each 16-byte record carrying the sweep index of the trial that produced
