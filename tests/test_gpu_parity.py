@@ -162,6 +162,16 @@ def test_fp32_large_config_sampled(oracle):
     assert nev > 2000 and ndis <= 2
 
 
+def test_fp32_large_config_bench_move_size(oracle):
+    """The same system at the benchmark's tuned move size (max_disp 5.2,
+    about 43 % acceptance): most groups are decided through the speculative
+    fixed point rather than from bounds; every 61st move checked."""
+    from paper_1602_05716_amd import inputs
+    sy = inputs.large_fp32()
+    err, ndis, nev = _fp32_check(oracle, sy, 2, 0x5EED0003, 10.4, sample_every=61)
+    assert nev > 1000 and ndis <= 2
+
+
 def _abs_pair_sum(x, q, lB):
     """l_B sum_{i<j} |q_i q_j| / r_ij: the scale of the rounding error of any
     summation order of the total energy (the sum cancels heavily)."""
