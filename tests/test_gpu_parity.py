@@ -172,6 +172,17 @@ def test_fp32_large_config_bench_move_size(oracle):
     assert nev > 1000 and ndis <= 2
 
 
+def test_fp32_2to1_full_size_sampled(oracle):
+    """2:1, N = 98304 (32768 at +2 with sigma 1.0, 65536 at -1 with sigma
+    0.8), phi = 0.1, l_B = 0.7: per-ion diameters, three targets per
+    workgroup and sweep; one sweep, every 97th move checked against the
+    exact double dE."""
+    from paper_1602_05716_amd import inputs
+    sy = inputs.asymmetric_2to1()
+    err, ndis, nev = _fp32_check(oracle, sy, 1, 0x5EED0005, 1.0, sample_every=97)
+    assert nev > 1000 and ndis <= 2
+
+
 def _abs_pair_sum(x, q, lB):
     """l_B sum_{i<j} |q_i q_j| / r_ij: the scale of the rounding error of any
     summation order of the total energy (the sum cancels heavily)."""
