@@ -508,8 +508,8 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
     // than the rounding of these sums) and no hard-core overlap can flip, the
     // group's decisions are certain and are published before the band
     // groups' accept masks have even arrived; the exact dE follows.
-    // Otherwise: wait for the band groups and iterate the sequential rule to
-    // its fixed point.
+    // Otherwise: solve the sequential rule's fixed point for a guess of the
+    // pending masks, then correct it as the true masks arrive (below).
     __builtin_amdgcn_s_setprio(3);
     const double lq = mi.lq;
     const bool can = valid && !wall && !ovb;
