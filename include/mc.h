@@ -289,7 +289,9 @@ int mc_chain_set_max_disp(mc_handle* h, int32_t chain, double max_disp);
 
 /*
  * Schedule of the batch: workgroups [n_chains] (nullable) receives each
- * chain's workgroup count; model [2] (nullable) the cost model in use,
+ * chain's workgroup count (chains with count 1 may share their workgroup
+ * with other such chains, see mc_autotune, so the counts can add up to more
+ * than the launch's workgroups); model [2] (nullable) the cost model in use,
  * a and b in microseconds, of the per-sweep time t(B, w) = a B + b B^2 / w
  * of a chain of B groups of 64 ions served by w workgroups.  Schedules only
  * change speed: a chain's trajectory does not depend on them.
@@ -297,7 +299,8 @@ int mc_chain_set_max_disp(mc_handle* h, int32_t chain, double max_disp);
 int mc_get_schedule(const mc_handle* h, int32_t* workgroups, double* model);
 
 /* Sets each chain's workgroup count, workgroups [n_chains], each in
- * [1, groups of 64 of the chain], total at most the co-resident capacity. */
+ * [1, groups of 64 of the chain], total at most the co-resident capacity;
+ * every workgroup serves one chain. */
 int mc_set_schedule(mc_handle* h, const int32_t* workgroups);
 
 /* Synchronises and reports, per chain, the device time in milliseconds of
@@ -308,10 +311,13 @@ int mc_chain_launch_ms(mc_handle* h, double* ms);
 /*
  * Autotuner: runs one launch of calib_sweeps sweeps of every chain (real
  * sweeps that continue the chains, keyed by seed), fits the cost model's a
- * and b to the measured per-chain times by least squares on relative error,
- * then gives each chain workgroups by water filling of the co-resident
- * capacity (each step gives one more workgroup to the chain the model says
- * finishes last).  model [2] (nullable) receives the fit.
+ * and b to the measured per-chain times by least squares on relative error
+ * (a held within [0.3, 4] us), and gives each chain a factor: its measured
+ * time over the model's prediction.  It then re-plans for the smallest
+ * sweep time T that fits the co-resident capacity: chains that one
+ * workgroup brings within T share workgroups (each runs its chains one
+ * after another), every other chain gets the fewest workgroups that bring
+ * it within T.  model [2] (nullable) receives the fit.
  */
 int mc_autotune(mc_handle* h, int32_t calib_sweeps, uint64_t seed, double* model);
 
