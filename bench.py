@@ -222,7 +222,8 @@ def da_leg(args, md):
     n_log = sweeps_log * n
     seed = 0x5EED0005
     with mc.Chain(system.xyz, system.q, system.sigma, system.R, system.lB, precision="fp32", max_disp=md,
-                  resum_every=100, waves=4, log_moves=n_log, hip_stream=stream.cuda_stream) as lg_chain:
+                  resum_every=100, waves=4, log_moves=n_log, hip_stream=stream.cuda_stream,
+                  band=args.da_band) as lg_chain:
         lg_chain.sweep(sweeps_log, seed)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -240,6 +241,7 @@ def da_leg(args, md):
                   rdf_rmax=10.0)
         if mode == "da":
             kw["waves"] = 4
+            kw["band"] = args.da_band
         with mc.Chain(x0, system.q, system.sigma, system.R, system.lB, **kw) as c:
             if mode == "da":
                 c.set_surrogate(tr["params"], tr["ref_stage2_reject"], True)
@@ -290,6 +292,8 @@ def main():
     ap.add_argument("--da-log-moves", type=int, default=1000000)
     ap.add_argument("--da-epochs", type=int, default=6)
     ap.add_argument("--da-sweeps", type=int, default=400)
+    ap.add_argument("--da-band", type=int, default=-1,
+                    help="band of the logging and surrogate chains (-1: the library's default)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
