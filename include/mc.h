@@ -309,6 +309,22 @@ int mc_set_schedule(mc_handle* h, const int32_t* workgroups);
 int mc_chain_launch_ms(mc_handle* h, double* ms);
 
 /*
+ * The batch planner on its own (host only; no device or handle): the plan
+ * mc_autotune and mc_create_batch make for n_chains chains of nb[k] 64-ion
+ * groups, cost factors scale[k] (nullable: 1) and measured[k] (nullable:
+ * none measured; only measured chains may share a workgroup), cost model
+ * a, b (microseconds, both > 0) and budget >= n_chains workgroups.  Fills
+ * workgroups[n_chains] and *n_launch (workgroups of the launch); if any of
+ * item_chain, item_index, item_wg [max_items] is given, the launch's items:
+ * item q is workgroup item_index[q] of chain item_chain[q], run by launch
+ * workgroup item_wg[q] (a launch workgroup runs its items in order).
+ * MC_E_ARG on bad arguments or too few max_items.
+ */
+int mc_plan_schedule(int32_t n_chains, const int32_t* nb, const double* scale, const uint8_t* measured,
+                     double a, double b, int32_t budget, int32_t* workgroups, int32_t* n_launch,
+                     int32_t* item_chain, int32_t* item_index, int32_t* item_wg, int32_t max_items);
+
+/*
  * Autotuner: runs one launch of calib_sweeps sweeps of every chain (real
  * sweeps that continue the chains, keyed by seed), fits the cost model's a
  * and b to the measured per-chain times by least squares on relative error

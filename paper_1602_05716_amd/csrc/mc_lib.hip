@@ -393,9 +393,6 @@ struct ArenaPlan {
     }
 };
 
-double chain_cost(const mc_handle* h, const Chain& c, int w) {
-    return c.cost_scale * (h->model_a * c.nb + h->model_b * (double)c.nb * c.nb / std::max(1, w));
-}
 
 // A workgroup's items: (chain, index of the workgroup among the chain's).
 using WgLists = std::vector<std::vector<int2>>;
@@ -409,6 +406,17 @@ void order_grid(std::vector<std::pair<double, std::vector<int2>>>& per, WgLists&
     lists.assign(W, {});
     for (int q = 0; q < W; ++q) lists[q < half ? q : W - 1 - (q - half)] = std::move(per[q].second);
 }
+// What the planner needs of each chain.
+struct PlanChain {
+    int nb;           // groups of 64
+    double scale;     // measured cost factor (1 until measured)
+    bool measured;
+};
+
+double plan_cost(const PlanChain& c, double a, double b, int w) {
+    return c.scale * (a * c.nb + b * (double)c.nb * c.nb / std::max(1, w));
+}
+
 // Workgroups per chain and the grid, on the cost model, for a target sweep
 // time T.  A chain whose cost was measured (autotuner) and that one
 // workgroup brings within T shares a workgroup with others: first fit by
@@ -416,15 +424,14 @@ void order_grid(std::vector<std::pair<double, std::vector<int2>>>& per, WgLists&
 // other chain gets the fewest workgroups that bring it within T (at most one
 // per group).  T is the smallest value (bisection) whose plan fits the
 // budget; workgroups left over go, one at a time, to the multi-workgroup
-// chain predicted to finish last.
-void plan_schedule(mc_handle* h, std::vector<int>& wg, WgLists& lists) {
-    const int nc = (int)h->chains.size();
-    const int budget = h->da_kernel ? std::min(h->wg_budget, h->cap_da) : h->wg_budget;
+// chain predicted to finish last.  Host only.
+void plan_lists(const std::vector<PlanChain>& ch, double ma, double mb, int budget, std::vector<int>& wg,
+                WgLists& lists) {
+    const int nc = (int)ch.size();
+    auto cost = [&](int k, int w) { return plan_cost(ch[k], ma, mb, w); };
     std::vector<int> order(nc);
     for (int k = 0; k < nc; ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        return chain_cost(h, h->chains[x], 1) > chain_cost(h, h->chains[y], 1);
-    });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x, 1) > cost(y, 1); });
     std::vector<double> bin_t;
     std::vector<std::vector<int2>> bin_items;
     auto plan = [&](double T, std::vector<int>& w) {
@@ -433,12 +440,14 @@ void plan_schedule(mc_handle* h, std::vector<int>& wg, WgLists& lists) {
         bin_items.clear();
         int used = 0;
         for (int k : order) {
-            const Chain& c = h->chains[k];
-            const double t1 = chain_cost(h, c, 1);
-            if (t1 > T || !c.measured) {
-                int need = c.nb;
-                for (int ww = 1; ww <= c.nb; ++ww)
-                    if (chain_cost(h, c, ww) <= T) { need = ww; break; }
+            const double t1 = cost(k, 1);
+            if (t1 > T || !ch[k].measured) {
+                int need = ch[k].nb;
+                for (int ww = 1; ww <= ch[k].nb; ++ww)
+                    if (cost(k, ww) <= T) {
+                        need = ww;
+                        break;
+                    }
                 w[k] = need;
                 used += need;
             } else {
@@ -456,40 +465,51 @@ void plan_schedule(mc_handle* h, std::vector<int>& wg, WgLists& lists) {
         return used + (int)bin_t.size();
     };
     double lo = 0.0, hi = 0.0;
-    for (int k = 0; k < nc; ++k) hi = std::max(hi, chain_cost(h, h->chains[k], 1));
+    for (int k = 0; k < nc; ++k) hi = std::max(hi, cost(k, 1));
     for (int it = 0; it < 50; ++it) {
         const double mid = 0.5 * (lo + hi);
         std::vector<int> w;
-        if (plan(mid, w) <= budget) hi = mid; else lo = mid;
+        if (plan(mid, w) <= budget)
+            hi = mid;
+        else
+            lo = mid;
     }
     int used = plan(hi, wg);
     std::vector<char> packed(nc, 0);
-    for (const auto& b : bin_items)
-        for (const int2& it : b) packed[it.x] = 1;
+    for (const auto& bi : bin_items)
+        for (const int2& it : bi) packed[it.x] = 1;
     using Item = std::pair<double, int>;
     std::priority_queue<Item> pq;
     for (int k = 0; k < nc; ++k)
-        if (!packed[k] && wg[k] < h->chains[k].nb) pq.emplace(chain_cost(h, h->chains[k], wg[k]), k);
+        if (!packed[k] && wg[k] < ch[k].nb) pq.emplace(cost(k, wg[k]), k);
     while (used < budget && !pq.empty()) {
         const int k = pq.top().second;
         pq.pop();
         wg[k] += 1;
         used += 1;
-        if (wg[k] < h->chains[k].nb) pq.emplace(chain_cost(h, h->chains[k], wg[k]), k);
+        if (wg[k] < ch[k].nb) pq.emplace(cost(k, wg[k]), k);
     }
     std::vector<std::pair<double, std::vector<int2>>> per;
     for (int k = 0; k < nc; ++k) {
         if (packed[k]) continue;
-        const double work = (double)h->chains[k].nb * h->chains[k].nb / wg[k];
+        const double work = (double)ch[k].nb * ch[k].nb / wg[k];
         for (int j = 0; j < wg[k]; ++j) per.emplace_back(work, std::vector<int2>{make_int2(k, j)});
     }
     for (size_t q = 0; q < bin_items.size(); ++q) {
         double work = 0.0;
-        for (const int2& it : bin_items[q]) work += (double)h->chains[it.x].nb * h->chains[it.x].nb;
+        for (const int2& it : bin_items[q]) work += (double)ch[it.x].nb * ch[it.x].nb;
         per.emplace_back(work, bin_items[q]);
     }
     order_grid(per, lists);
 }
+
+void plan_schedule(mc_handle* h, std::vector<int>& wg, WgLists& lists) {
+    std::vector<PlanChain> ch;
+    for (const Chain& c : h->chains) ch.push_back(PlanChain{c.nb, c.cost_scale, c.measured});
+    const int budget = h->da_kernel ? std::min(h->wg_budget, h->cap_da) : h->wg_budget;
+    plan_lists(ch, h->model_a, h->model_b, budget, wg, lists);
+}
+
 // Fills every chain's descriptor from the host state.
 void fill_desc(mc_handle* h) {
     for (Chain& c : h->chains) {
@@ -1360,6 +1380,38 @@ int mc_set_schedule(mc_handle* h, const int32_t* workgroups) {
     WgLists lists;
     order_grid(per, lists);
     return apply_schedule(h, wg, lists);
+}
+
+int mc_plan_schedule(int32_t n_chains, const int32_t* nb, const double* scale, const uint8_t* measured,
+                     double a, double b, int32_t budget, int32_t* workgroups, int32_t* n_launch,
+                     int32_t* item_chain, int32_t* item_index, int32_t* item_wg, int32_t max_items) {
+    if (n_chains < 1 || !nb || !workgroups || !n_launch || budget < n_chains || !(a > 0) || !(b > 0) ||
+        !is_finite(a) || !is_finite(b))
+        return MC_E_ARG;
+    std::vector<PlanChain> ch(n_chains);
+    for (int k = 0; k < n_chains; ++k) {
+        if (nb[k] < 1) return MC_E_ARG;
+        const double sc = scale ? scale[k] : 1.0;
+        if (!(sc > 0) || !is_finite(sc)) return MC_E_ARG;
+        ch[k] = PlanChain{nb[k], sc, measured ? measured[k] != 0 : false};
+    }
+    std::vector<int> wg;
+    WgLists lists;
+    plan_lists(ch, a, b, budget, wg, lists);
+    size_t items = 0;
+    for (const auto& l : lists) items += l.size();
+    if (items > (size_t)std::max(0, max_items) && (item_chain || item_index || item_wg)) return MC_E_ARG;
+    for (int k = 0; k < n_chains; ++k) workgroups[k] = wg[k];
+    *n_launch = (int32_t)lists.size();
+    size_t q = 0;
+    for (size_t w = 0; w < lists.size(); ++w)
+        for (const int2& it : lists[w]) {
+            if (item_chain) item_chain[q] = it.x;
+            if (item_index) item_index[q] = it.y;
+            if (item_wg) item_wg[q] = (int32_t)w;
+            ++q;
+        }
+    return MC_OK;
 }
 
 int mc_chain_launch_ms(mc_handle* h, double* ms) {

@@ -76,7 +76,7 @@ SYMBOLS = ["mc_options_init", "mc_create", "mc_sweep", "mc_energy", "mc_rdf", "m
            "mc_create_batch", "mc_chain_count", "mc_chain_energy", "mc_chain_rdf", "mc_chain_species",
            "mc_chain_positions", "mc_chain_trace", "mc_chain_energy_series", "mc_chain_stats",
            "mc_chain_set_max_disp", "mc_get_schedule", "mc_set_schedule", "mc_chain_launch_ms",
-           "mc_autotune", "mc_set_surrogate", "mc_get_log", "mc_mlp_grad", "mc_train_surrogate",
+           "mc_autotune", "mc_plan_schedule", "mc_set_surrogate", "mc_get_log", "mc_mlp_grad", "mc_train_surrogate",
            "mc_destroy", "mc_last_error"]
 
 DA_NPARAM = 33153
@@ -125,6 +125,8 @@ def load(path: str = LIB_PATH):
         "mc_set_schedule": ([_hp, _i32p], ctypes.c_int),
         "mc_chain_launch_ms": ([_hp, _f64p], ctypes.c_int),
         "mc_autotune": ([_hp, ctypes.c_int32, ctypes.c_uint64, _f64p], ctypes.c_int),
+        "mc_plan_schedule": ([ctypes.c_int32, _i32p, _f64p, _u8p, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                              _i32p, _i32p, _i32p, _i32p, _i32p, ctypes.c_int32], ctypes.c_int),
         "mc_set_surrogate": ([_hp, ctypes.c_int32, _f64p, ctypes.c_double, ctypes.c_int32], ctypes.c_int),
         "mc_get_log": ([_hp, ctypes.c_int32, ctypes.c_int64, _u8p, _f64p, _f64p, _u8p], ctypes.c_int),
         "mc_mlp_grad": ([ctypes.c_int32, _u8p, _f64p, _f64p, _f64p, _f64p], ctypes.c_int),
@@ -449,6 +451,26 @@ Chain.set_surrogate = _set_surrogate
 Chain.get_log = _get_log
 Batch.set_surrogate = _set_surrogate
 Batch.get_log = _get_log
+
+
+def plan_schedule(nb, scale=None, measured=None, a=1.2, b=1.3, budget=512):
+    """The batch planner alone (mc_plan_schedule, host only): returns
+    (workgroups per chain, launch items as rows (chain, index, launch workgroup))."""
+    nb = np.ascontiguousarray(nb, np.int32)
+    n = len(nb)
+    sc = None if scale is None else np.ascontiguousarray(scale, np.float64)
+    me = None if measured is None else np.ascontiguousarray(measured, np.uint8)
+    wg = np.zeros(n, np.int32)
+    nl = ctypes.c_int32()
+    cap = max(int(budget), 1) + n
+    items = np.zeros((3, cap), np.int32)
+    rc = lib().mc_plan_schedule(n, _p(nb, _i32p), None if sc is None else _p(sc, _f64p),
+                                None if me is None else _p(me, _u8p), a, b, budget, _p(wg, _i32p), ctypes.byref(nl),
+                                _p(items[0], _i32p), _p(items[1], _i32p), _p(items[2], _i32p), cap)
+    if rc != MC_OK:
+        raise MCError(rc, "mc_plan_schedule failed")
+    k = int(wg.sum())
+    return wg, items[:, :k].T.copy(), int(nl.value)
 
 
 def mlp_grad(feats, target, params):
