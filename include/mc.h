@@ -141,6 +141,21 @@ int mc_create(int32_t n, const double* charges, const double* diameters,
 int mc_sweep(mc_handle* h, int64_t n_sweeps, uint64_t seed);
 
 /*
+ * The same n_sweeps sweeps as mc_sweep (same trials, same random stream,
+ * same results up to the rounding order of the sums), run by the per-move
+ * parallel-reduction scheme that the paper benchmarks against (Sec. 4): one
+ * kernel launch per trial move, each thread one partner, a workgroup
+ * reduction, and the last workgroup to finish deciding the move.  A
+ * comparison baseline, far slower than mc_sweep.  It advances the same state
+ * (positions, running energy, trace, counters; the iteration and early-group
+ * counters stay unchanged), so it may take turns with mc_sweep on one chain,
+ * and takes record_timing, re-sum and g(r) intervals as mc_sweep does.
+ * Single-chain handles only, without a delayed-acceptance stage or move log:
+ * MC_E_ARG otherwise.  Asynchronous like mc_sweep.
+ */
+int mc_sweep_reduction(mc_handle* h, int64_t n_sweeps, uint64_t seed);
+
+/*
  * Synchronises and returns the running energy (sum of accepted dE since the
  * last re-sum, plus that re-sum) in *e_running, and, if e_exact is not NULL,
  * a fresh double-precision re-sum of the total energy of the current state

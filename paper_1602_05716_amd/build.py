@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmc.so")
 PEAK_EXE = os.path.join(HERE, "valu_peak")
 SOURCES = ["mc_lib.hip", "mc_train.hip"]
-HEADERS = ["mc_device.hpp", "mc_sweep_kernel.hpp", "mc_aux_kernels.hpp", "mc_internal.hpp"]
+HEADERS = ["mc_device.hpp", "mc_sweep_kernel.hpp", "mc_aux_kernels.hpp", "mc_reduce_kernel.hpp", "mc_internal.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -25,6 +25,7 @@
 #include "../../include/mc.h"
 #include "mc_aux_kernels.hpp"
 #include "mc_internal.hpp"
+#include "mc_reduce_kernel.hpp"
 #include "mc_sweep_kernel.hpp"
 
 using namespace mcdev;
@@ -188,6 +189,10 @@ struct mc_handle {
     int64_t t_launches = 0, t_sweeps = 0;
     double t_ms = 0.0;
     int64_t last_launch_sweeps = 0;
+    // per-move parallel-reduction scheme (allocated on first use)
+    ReducePart* d_rparts = nullptr;  // [r_blocks]
+    ReduceCtl* d_rctl = nullptr;
+    int r_blocks = 0;
 };
 
 namespace {
@@ -243,6 +248,10 @@ void free_all(mc_handle* h) {
     }
     if (h->arena) (void)hipFree(h->arena);
     h->arena = nullptr;
+    if (h->d_rparts) (void)hipFree(h->d_rparts);
+    if (h->d_rctl) (void)hipFree(h->d_rctl);
+    h->d_rparts = nullptr;
+    h->d_rctl = nullptr;
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     h->stream = nullptr;
 }
@@ -257,7 +266,7 @@ int sync_check(mc_handle* h) {
     if (ab != 0) {
         return fail(h, ab == MC_E_TIMEOUT ? MC_E_TIMEOUT : ab == MC_E_STATE ? MC_E_STATE : MC_E_DEVICE,
                     ab == MC_E_TIMEOUT ? "a device-side wait timed out (chain state is invalid)"
-                    : ab == MC_E_STATE ? "a group record was reused before it was read (chain state is invalid)"
+                    : ab == MC_E_STATE ? "a group record or position was not the one expected (chain state is invalid)"
                                        : "device reported an error");
     }
     return MC_OK;
@@ -634,13 +643,8 @@ int launch_rdf(mc_handle* h) {
     return MC_OK;
 }
 
-int launch_sweeps(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
-    if (n_sweeps <= 0) return MC_OK;
-    if (n_sweeps > kMaxLaunchSweeps) {
-        int rc = launch_sweeps(h, kMaxLaunchSweeps, seed);
-        if (rc) return rc;
-        return launch_sweeps(h, n_sweeps - kMaxLaunchSweeps, seed);
-    }
+// Buffers sized for a launch of n_sweeps sweeps and descriptors carrying the seed.
+int prepare_launch(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
     bool changed = false;
     for (Chain& c : h->chains) {
         const int64_t s_cap = c.e_capacity, d_cap = c.de_capacity;
@@ -656,6 +660,28 @@ int launch_sweeps(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
         int rc = upload_desc(h);
         if (rc) return rc;
     }
+    return MC_OK;
+}
+
+// Running energies of the launch's sweeps, then the host's sweep count.
+int finish_launch(mc_handle* h, int64_t n_sweeps) {
+    hipLaunchKernelGGL(energy_scan_kernel, dim3((unsigned)h->chains.size()), dim3(256), 0, h->stream, h->d_desc,
+                       (int32_t)n_sweeps, (int64_t)h->sweeps);
+    HIPCHECK(h, hipGetLastError());
+    h->sweeps += n_sweeps;
+    h->last_launch_sweeps = n_sweeps;
+    return MC_OK;
+}
+
+int launch_sweeps(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
+    if (n_sweeps <= 0) return MC_OK;
+    if (n_sweeps > kMaxLaunchSweeps) {
+        int rc = launch_sweeps(h, kMaxLaunchSweeps, seed);
+        if (rc) return rc;
+        return launch_sweeps(h, n_sweeps - kMaxLaunchSweeps, seed);
+    }
+    int rc = prepare_launch(h, n_sweeps, seed);
+    if (rc) return rc;
     SweepFn fn = pick_sweep(h->fp64, h->waves, h->uniform_sigma, h->da_kernel);
     Ctl ctl;
     ctl.abort = h->abort_flag;
@@ -679,15 +705,67 @@ int launch_sweeps(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
         h->ev_pending.emplace_back(e0, e1);
         h->ev_sweeps.push_back(n_sweeps);
     }
-    hipLaunchKernelGGL(energy_scan_kernel, dim3((unsigned)h->chains.size()), dim3(256), 0, h->stream, h->d_desc,
-                       (int32_t)n_sweeps, (int64_t)h->sweeps);
-    HIPCHECK(h, hipGetLastError());
-    h->sweeps += n_sweeps;
-    h->last_launch_sweeps = n_sweeps;
-    return MC_OK;
+    return finish_launch(h, n_sweeps);
 }
 
-int sweep_all(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
+// The per-move parallel-reduction scheme: one launch per trial move, on the
+// state of the single chain of the handle.
+int launch_reduction(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
+    if (n_sweeps <= 0) return MC_OK;
+    if (n_sweeps > kMaxLaunchSweeps) {
+        int rc = launch_reduction(h, kMaxLaunchSweeps, seed);
+        if (rc) return rc;
+        return launch_reduction(h, n_sweeps - kMaxLaunchSweeps, seed);
+    }
+    int rc = prepare_launch(h, n_sweeps, seed);
+    if (rc) return rc;
+    const Chain& c = h->chains[0];
+    const int nblk = (c.npad + kReduceThreads - 1) / kReduceThreads;
+    if (nblk > h->r_blocks) {
+        if (h->d_rparts) HIPCHECK(h, hipFree(h->d_rparts));
+        h->d_rparts = nullptr;
+        h->r_blocks = 0;
+        if ((rc = dalloc(h, &h->d_rparts, sizeof(ReducePart) * nblk))) return rc;
+        HIPCHECK(h, hipMemsetAsync(h->d_rparts, 0, sizeof(ReducePart) * nblk, h->stream));
+        h->r_blocks = nblk;
+    }
+    if (!h->d_rctl) {
+        if ((rc = dalloc(h, &h->d_rctl, sizeof(ReduceCtl)))) return rc;
+        HIPCHECK(h, hipMemsetAsync(h->d_rctl, 0, sizeof(ReduceCtl), h->stream));
+    }
+    Ctl ctl;
+    ctl.abort = h->abort_flag;
+    ctl.timeout_ticks = (uint64_t)(h->opt.wait_timeout_s * h->dev.wall_clock_hz);
+    const uint32_t s0 = (uint32_t)h->sweeps;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->opt.record_timing) {
+        HIPCHECK(h, hipEventCreate(&e0));
+        HIPCHECK(h, hipEventCreate(&e1));
+        HIPCHECK(h, hipEventRecord(e0, h->stream));
+    }
+    for (int64_t k = 0; k < n_sweeps; ++k) {
+        const uint32_t s = s0 + (uint32_t)k;
+        for (int32_t i = 0; i < c.n; ++i) {
+            if (h->fp64)
+                hipLaunchKernelGGL(reduce_move_kernel<double>, dim3(nblk), dim3(kReduceThreads), 0, h->stream,
+                                   h->d_desc, h->d_rparts, h->d_rctl, s, i, s0, ctl);
+            else
+                hipLaunchKernelGGL(reduce_move_kernel<float>, dim3(nblk), dim3(kReduceThreads), 0, h->stream,
+                                   h->d_desc, h->d_rparts, h->d_rctl, s, i, s0, ctl);
+        }
+        HIPCHECK(h, hipGetLastError());
+    }
+    if (h->opt.record_timing) {
+        HIPCHECK(h, hipEventRecord(e1, h->stream));
+        h->ev_pending.emplace_back(e0, e1);
+        h->ev_sweeps.push_back(n_sweeps);
+    }
+    return finish_launch(h, n_sweeps);
+}
+
+using LaunchFn = int (*)(mc_handle*, int64_t, uint64_t);
+
+int sweep_all(mc_handle* h, int64_t n_sweeps, uint64_t seed, LaunchFn launch = launch_sweeps) {
     if (n_sweeps < 0 || h->sweeps + n_sweeps > (int64_t)UINT32_MAX)
         return fail(h, MC_E_ARG, "n_sweeps out of range");
     int64_t left = n_sweeps;
@@ -698,7 +776,7 @@ int sweep_all(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
         if (rd > 0) step = std::min<int64_t>(step, rd - h->sweeps % rd);
         const int dw = h->da_window;  // the drift monitor judges at window ends
         if (dw > 0) step = std::min<int64_t>(step, dw - h->sweeps % dw);
-        int rc = launch_sweeps(h, step, seed);
+        int rc = launch(h, step, seed);
         if (rc) return rc;
         left -= step;
         if (re > 0 && h->sweeps % re == 0 && (rc = launch_energy(h, 1, 1))) return rc;
@@ -1240,6 +1318,15 @@ int mc_sweep(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
     if (!h) return MC_E_ARG;
     if (h->failed) return fail(h, MC_E_STATE, "handle is in a failed state: " + h->err);
     return sweep_all(h, n_sweeps, seed);
+}
+
+int mc_sweep_reduction(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
+    if (!h) return MC_E_ARG;
+    if (h->failed) return fail(h, MC_E_STATE, "handle is in a failed state: " + h->err);
+    if (h->chains.size() != 1) return fail(h, MC_E_ARG, "the per-move reduction scheme takes a single-chain handle");
+    if (h->da_kernel)
+        return fail(h, MC_E_ARG, "the per-move reduction scheme has no delayed-acceptance stage or move log");
+    return sweep_all(h, n_sweeps, seed, launch_reduction);
 }
 
 int mc_energy(mc_handle* h, double* e_running, double* e_exact) { return chain_energy(h, 0, e_running, e_exact); }

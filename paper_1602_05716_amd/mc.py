@@ -70,7 +70,7 @@ class ChainSpec(ctypes.Structure):
 
 
 # Every symbol include/mc.h declares.
-SYMBOLS = ["mc_options_init", "mc_create", "mc_sweep", "mc_energy", "mc_rdf", "mc_rdf_sample",
+SYMBOLS = ["mc_options_init", "mc_create", "mc_sweep", "mc_sweep_reduction", "mc_energy", "mc_rdf", "mc_rdf_sample",
            "mc_rdf_reset", "mc_species", "mc_get_positions", "mc_trace", "mc_energy_series",
            "mc_get_stats", "mc_timing", "mc_timing_reset", "mc_set_max_disp",
            "mc_create_batch", "mc_chain_count", "mc_chain_energy", "mc_chain_rdf", "mc_chain_species",
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
         "mc_create": ([ctypes.c_int32, _f64p, _f64p, _f64p, ctypes.c_double, ctypes.c_double,
                        ctypes.POINTER(Options), ctypes.POINTER(_hp)], ctypes.c_int),
         "mc_sweep": ([_hp, ctypes.c_int64, ctypes.c_uint64], ctypes.c_int),
+        "mc_sweep_reduction": ([_hp, ctypes.c_int64, ctypes.c_uint64], ctypes.c_int),
         "mc_energy": ([_hp, _f64p, _f64p], ctypes.c_int),
         "mc_rdf": ([_hp, ctypes.c_int32, _f64p, _u64p, _u64p, _i64p], ctypes.c_int),
         "mc_rdf_sample": ([_hp], ctypes.c_int),
@@ -190,6 +191,10 @@ class Chain:
 
     def sweep(self, n_sweeps, seed):
         self._check(self._L.mc_sweep(self.h, int(n_sweeps), int(seed)))
+
+    def sweep_reduction(self, n_sweeps, seed):
+        """The same sweeps by the per-move parallel-reduction scheme (mc_sweep_reduction)."""
+        self._check(self._L.mc_sweep_reduction(self.h, int(n_sweeps), int(seed)))
 
     def energy(self, exact=False):
         er = ctypes.c_double()

@@ -27,6 +27,13 @@ def test_header_symbols_exported():
     assert sorted(mc.SYMBOLS) == names
 
 
+def test_null_handles_are_rejected():
+    from paper_1602_05716_amd import mc
+    L = mc.lib()
+    assert L.mc_sweep(None, 1, 1) == -1
+    assert L.mc_sweep_reduction(None, 1, 1) == -1
+
+
 def test_options_defaults():
     from paper_1602_05716_amd import mc
     o = mc.options()
