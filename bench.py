@@ -187,6 +187,25 @@ def batched_leg(args, log_fn=None):
             "batched_over_sequential": t_seq / t_batch}
 
 
+def reduction_leg(chain, args, sweep_rate):
+    """The paper's GPU comparison code (Sec. 4): the same chain continued by
+    the per-move parallel-reduction scheme, one launch per trial move, after
+    the timed region (it does not touch the measured sweeps)."""
+    import torch
+    n = chain.n
+    chain.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chain.sweep_reduction(args.reduction_sweeps, args.seed + 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _, ms, _ = chain.timing()
+    moves = args.reduction_sweeps * n
+    return {"kernel": "reduce_move_kernel<float>", "sweeps": args.reduction_sweeps, "launches": moves,
+            "wall_s": wall, "event_s": ms * 1e-3, "moves_per_s": moves / wall, "us_per_move": 1e6 * wall / moves,
+            "sweep_kernel_over_reduction": sweep_rate / (moves / wall)}
+
+
 def _gr_sample_run(chain, sweeps, seed, every):
     """Runs `sweeps` sweeps with a g(r) sample every `every` sweeps; returns
     (wall seconds, energy series, g(r) of the first and second halves)."""
@@ -292,6 +311,9 @@ def main():
     ap.add_argument("--da-log-moves", type=int, default=1000000)
     ap.add_argument("--da-epochs", type=int, default=6)
     ap.add_argument("--da-sweeps", type=int, default=400)
+    ap.add_argument("--no-reduction", action="store_true",
+                    help="skip the per-move parallel-reduction comparison leg")
+    ap.add_argument("--reduction-sweeps", type=int, default=1)
     ap.add_argument("--da-band", type=int, default=-1,
                     help="band of the logging and surrogate chains (-1: the library's default)")
     args = ap.parse_args()
@@ -355,6 +377,10 @@ def main():
                 "kernel": "sweep_kernel<float,%d>" % st1["waves"],
                 "avg_launch_ms": avg_launch_s * 1e3, "launches": launches,
                 "sweeps_per_launch": kernel_sweeps / max(1, launches)}
+    reduction = None
+    if not args.no_reduction:
+        log("per-move parallel-reduction leg (%d sweep(s))" % args.reduction_sweeps)
+        reduction = reduction_leg(chain, args, moves / elapsed)
     probe = None if args.no_probe else run_valu_probe()
     if probe:
         roofline["probe"] = probe
@@ -395,6 +421,7 @@ def main():
                       "plain_same_run_as_da": da["plain"]["ess_per_s"] if da else None},
         "batched": batched,
         "surrogate_da": da,
+        "reduction_scheme": reduction,
         "energy": {"tau_int_sweeps": tau, "e_running": e_run, "e_resum": e_exact,
                    "max_abs_drift_per_resum": st1["max_abs_drift"]},
         "roofline": roofline,
