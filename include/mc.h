@@ -106,6 +106,11 @@ typedef struct mc_options {
     int64_t log_moves;      /* log features, dE and dEh of the first this many
                                moves of every chain for training (mc_get_log),
                                0 = off                                             */
+    double rdf_margin;      /* g(r) centres need |x| <= R - rdf_rmax - rdf_margin:
+                               every neighbour counted then lies at least
+                               rdf_margin inside the wall (Sec. 5.2 leaves ions
+                               within ten Debye lengths of the wall out of the
+                               data); default 0                                    */
 } mc_options;
 
 /* Fills *opt with the defaults.  Returns MC_E_ARG if opt is NULL. */
@@ -168,7 +173,7 @@ int mc_energy(mc_handle* h, double* e_running, double* e_exact);
  * Species are the distinct (charge, diameter) pairs, ordered by decreasing
  * charge then increasing diameter.  g [ntypes*ntypes*bins] receives
  * g_ab(r_k) = C_ab(k) / (Ncentre_a * n_b * V_k) (centres: ions with
- * |x| <= R - rmax; n_b = (N_b - delta_ab) / ((4/3) pi (R - sigma_b/2)^3);
+ * |x| <= R - rmax - rdf_margin; n_b = (N_b - delta_ab) / ((4/3) pi (R - sigma_b/2)^3);
  * V_k the shell volume); counts (nullable) [ntypes*ntypes*bins] the raw
  * integer pair counts; centres (nullable) [ntypes] the centre counts; bins
  * must equal the handle's rdf_bins.  *n_samples (nullable) gets the number of

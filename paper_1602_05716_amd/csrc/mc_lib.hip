@@ -551,7 +551,7 @@ void fill_desc(mc_handle* h) {
         d.e_capacity = c.e_capacity;
         d.type = c.d_type;
         d.ntypes = (int32_t)c.species.size();
-        d.rdf_rc = c.R - h->opt.rdf_rmax;
+        d.rdf_rc = c.R - h->opt.rdf_rmax - h->opt.rdf_margin;
         d.rdf_counts = c.rdf_counts;
         d.rdf_centres = c.rdf_centres;
         d.da_w = c.da_w;
@@ -1044,6 +1044,8 @@ int check_options(const mc_options& opt) {
     if (opt.resum_every < 0 || opt.rdf_every < 0) return fail(nullptr, MC_E_ARG, "negative interval");
     if (opt.rdf_bins < 1 || opt.rdf_bins > 4096 || !is_finite(opt.rdf_rmax) || opt.rdf_rmax <= 0)
         return fail(nullptr, MC_E_ARG, "rdf_bins must be in [1, 4096] and rdf_rmax > 0");
+    if (!is_finite(opt.rdf_margin) || opt.rdf_margin < 0)
+        return fail(nullptr, MC_E_ARG, "rdf_margin must be finite and >= 0");
     if (opt.band < -1 || opt.band > kMaxBand) return fail(nullptr, MC_E_ARG, "band out of range");
     if (opt.waves != 0 && opt.waves != 4 && opt.waves != 8) return fail(nullptr, MC_E_ARG, "waves must be 0, 4 or 8");
     if (opt.workgroups < 0 || opt.trace_moves < 0) return fail(nullptr, MC_E_ARG, "negative count");
@@ -1263,6 +1265,7 @@ int mc_options_init(mc_options* o) {
     o->rdf_every = 0;
     o->rdf_bins = 200;
     o->rdf_rmax = 10.0;
+    o->rdf_margin = 0.0;
     o->chain_id = 0;
     o->hip_stream = nullptr;
     o->band = -1;

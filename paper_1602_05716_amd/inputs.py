@@ -172,3 +172,35 @@ def ensemble_chain(n: int, phi: float, lB: float, seed: int) -> System:
     s.xyz = random_start(s, seed)
     s.meta.update(seed=seed)
     return s
+
+
+# The paper's production electrolyte (Sec. 5.2): 3:-1, ion diameter 7.5 A
+# (radius 3.75 A), Bjerrum length 7.117 A, bare Debye length 28.53 A.  In
+# units of the diameter: l_B = 7.117 / 7.5; the cation density follows from
+# kappa^2 = 4 pi l_B (n_+ 9 + n_- 1) with n_- = 3 n_+.
+PAPER_DIAMETER_A = 7.5
+PAPER_BJERRUM_A = 7.117
+PAPER_DEBYE_A = 28.53
+
+
+def three_to_one_density() -> tuple[float, float]:
+    """(n_+, n_-) in ions per diameter^3 of the paper's 3:-1 system."""
+    lB = PAPER_BJERRUM_A / PAPER_DIAMETER_A
+    kappa = PAPER_DIAMETER_A / PAPER_DEBYE_A
+    n_plus = kappa * kappa / (4.0 * np.pi * lB * (9.0 + 3.0))
+    return n_plus, 3.0 * n_plus
+
+
+def three_to_one(n: int = 1 << 20, seed: int = 0x5EED0007) -> System:
+    """The paper's 3:-1 system with n ions (n / 4 at +3, 3 n / 4 at -1, all
+    of diameter 1 = 7.5 A), at its density (phi = (n_+ + n_-) pi / 6, about
+    1.0e-3), in a hard-wall sphere; uniform random start without overlap."""
+    if n % 4:
+        raise ValueError("n must be a multiple of 4")
+    n_plus, n_minus = three_to_one_density()
+    phi = (n_plus + n_minus) * np.pi / 6.0
+    s = electrolyte(n // 4, 3 * n // 4, 3.0, -1.0, 1.0, 1.0, phi, PAPER_BJERRUM_A / PAPER_DIAMETER_A,
+                    name=f"3:-1 N={n} (paper's production system, diameter 7.5 A)")
+    s.xyz = random_start(s, seed)
+    s.meta.update(seed=seed, kappa_inv=PAPER_DEBYE_A / PAPER_DIAMETER_A, phi=phi)
+    return s

@@ -40,7 +40,7 @@ class Options(ctypes.Structure):
                 ("workgroups", ctypes.c_int32), ("trace_moves", ctypes.c_int64),
                 ("wait_timeout_s", ctypes.c_double), ("record_timing", ctypes.c_int32),
                 ("da_rcut", ctypes.c_double), ("da_window", ctypes.c_int32), ("da_delta", ctypes.c_double),
-                ("log_moves", ctypes.c_int64)]
+                ("log_moves", ctypes.c_int64), ("rdf_margin", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):

@@ -38,7 +38,7 @@ def test_options_defaults():
     from paper_1602_05716_amd import mc
     o = mc.options()
     assert o.precision == mc.MC_FP32_ACC64 and o.max_disp == 0.5 and o.resum_every == 100
-    assert o.rdf_bins == 200 and o.rdf_rmax == 10.0 and o.band == -1
+    assert o.rdf_bins == 200 and o.rdf_rmax == 10.0 and o.band == -1 and o.rdf_margin == 0.0
     assert mc.lib().mc_options_init(None) == -1
 
 

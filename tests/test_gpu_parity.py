@@ -227,6 +227,24 @@ def test_rdf_counts_match_oracle(oracle):
     assert np.array_equal(r["counts"], c) and np.array_equal(r["centres"], ce)
 
 
+def test_rdf_margin_moves_the_centres_inward(oracle):
+    """rdf_margin: centres need |x| <= R - rmax - margin (the oracle's
+    centre rule at the radius R - margin)."""
+    from paper_1602_05716_amd import mc
+    sy = _sys(600, 1800, q=(3.0, -1.0), phi=0.02, seed=14)
+    _say("rdf margin N=2400")
+    with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision="fp32", rdf_every=3,
+                  rdf_bins=64, rdf_rmax=4.0, rdf_margin=3.5) as ch:
+        ch.sweep(3, 9)
+        x = ch.positions()
+        r = ch.rdf()
+    types, _ = sy.types()
+    c, ce = oracle.rdf_counts(x, types, 2, sy.R - 3.5, 4.0, 64)
+    c0, ce0 = oracle.rdf_counts(x, types, 2, sy.R, 4.0, 64)
+    assert r["samples"] == 1 and ce.sum() < ce0.sum()
+    assert np.array_equal(r["counts"], c) and np.array_equal(r["centres"], ce)
+
+
 def test_energy_series_and_stats(oracle):
     from paper_1602_05716_amd import mc
     sy = _sys(100, 100, seed=12)
