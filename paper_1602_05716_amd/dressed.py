@@ -13,7 +13,7 @@ raw counts, centre counts and the energy series go to ``--out`` (npz); the
 analysis is printed as one JSON line, lengths also in Angstrom (diameter
 7.5 A) beside the paper's values for context.
 
-    python -m paper_1602_05716_amd.dressed --n 262144 --sweeps 1000 --out gpurun_out/dressed.npz
+    python -m paper_1602_05716_amd.dressed --n 262144 --sweeps 1000 --out dressed.npz
 """
 from __future__ import annotations
 
