@@ -182,6 +182,28 @@ int mc_energy(mc_handle* h, double* e_running, double* e_exact);
 int mc_rdf(mc_handle* h, int32_t bins, double* g, uint64_t* counts, uint64_t* centres,
            int64_t* n_samples);
 
+/*
+ * Checkpoint and resume.  mc_save synchronises and writes the handle's state
+ * to the file at path: per chain the model (charges, diameters, wall radius,
+ * l_B, move size, chain id), the positions after the last two sweeps and
+ * the accept masks of the last groups (the sweep kernel's working state, so
+ * that a resumed chain sums every dE in the same order), the running energy
+ * and its re-sum record, the counters, the g(r) counts and samples, the
+ * energy series, and the handle's sweep counter and options.  Not saved: move
+ * traces, the delayed-acceptance network, log and monitor (install the
+ * network again with mc_set_surrogate), and the autotuned schedule (planned
+ * again from the defaults).  mc_load creates a handle from such a file; opt
+ * NULL means the saved options (without their stream), otherwise opt is used
+ * and must have the saved precision and rdf_bins.  The random stream is a
+ * function of (seed, sweep, ion, chain), so sweeps run after mc_load with the
+ * same seed reproduce the ones an uninterrupted chain would run, bit for bit.
+ * The file is in host byte order for this library version.  Errors: MC_E_ARG
+ * (bad path, unreadable or foreign file, mismatched options), then those of
+ * mc_create; on error *out is NULL.
+ */
+int mc_save(mc_handle* h, const char* path);
+int mc_load(const char* path, const mc_options* opt, mc_handle** out);
+
 /* Enqueues one g(r) sample of the current configuration. */
 int mc_rdf_sample(mc_handle* h);
 

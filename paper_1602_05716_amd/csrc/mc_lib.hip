@@ -308,7 +308,10 @@ bool find_overlap(int n, const double* x, const double* sigma, double smax, int*
 }
 
 // Host-side validation of one chain's inputs (before any device work).
-int validate_chain(const mc_chain_spec& sp, const mc_options& opt, const std::string& who) {
+// check_overlap false: the positions come from a chain's own state (a
+// checkpoint), whose float overlap test may round a contact either way.
+int validate_chain(const mc_chain_spec& sp, const mc_options& opt, const std::string& who,
+                   bool check_overlap = true) {
     const int32_t n = sp.n;
     if (n < 1 || n > (1 << 24)) return fail(nullptr, MC_E_ARG, who + "n out of range [1, 2^24]");
     if (!sp.charges || !sp.diameters || !sp.positions) return fail(nullptr, MC_E_ARG, who + "null input array");
@@ -335,7 +338,7 @@ int validate_chain(const mc_chain_spec& sp, const mc_options& opt, const std::st
             return fail(nullptr, MC_E_WALL, who + "ion " + std::to_string(i) + " crosses the wall");
     }
     int oa = -1, ob = -1;
-    if (find_overlap(n, sp.positions, sp.diameters, smax, &oa, &ob))
+    if (check_overlap && find_overlap(n, sp.positions, sp.diameters, smax, &oa, &ob))
         return fail(nullptr, MC_E_OVERLAP,
                     who + "ions " + std::to_string(oa) + " and " + std::to_string(ob) + " overlap");
     // species: distinct (q, sigma)
@@ -1254,6 +1257,119 @@ int mc_internal_log(mc_handle* h, int32_t chain, MCLogView* out) {
 
 int mc_internal_fail(mc_handle* h, int code, const char* msg) { return fail(h, code, msg); }
 
+namespace {
+
+// ---- checkpoints --------------------------------------------------------
+// File layout (host byte order): magic "MCCKPT01", then int32 version,
+// n_chains, sizeof(mc_options), ST_N; int64 sweeps, rdf_samples; the options
+// (hip_stream zeroed); per chain: int32 n, species, rdf_bins, chain_id;
+// double R, l_B, max_disp, running energy; EnergyAux; uint64 stats[ST_N];
+// double charges[n], diameters[n], positions[3n] (after the last sweep),
+// previous[3n] (after the one before); uint64 accept masks of the last kRing
+// groups (oldest first); uint64 counts[nt*nt*bins], centres[nt]; int64 m;
+// double energy_series[m].
+constexpr char kCkptMagic[8] = {'M', 'C', 'C', 'K', 'P', 'T', '0', '1'};
+constexpr int32_t kCkptVersion = 1;
+
+struct CkptChain {
+    int32_t n = 0, nt = 0, bins = 0;
+    uint32_t chain_id = 0;
+    double R = 0, lB = 0, max_disp = 0, e_run = 0;
+    EnergyAux aux{};
+    unsigned long long stats[ST_N] = {};
+    std::vector<double> q, sigma, xyz, prev, series;
+    std::vector<uint64_t> masks;  // [kRing], oldest group first
+    std::vector<unsigned long long> counts, centres;
+};
+
+struct File {
+    FILE* f = nullptr;
+    explicit File(FILE* x) : f(x) {}
+    ~File() {
+        if (f) fclose(f);
+    }
+    template <typename T> bool put(const T* v, size_t k) { return fwrite(v, sizeof(T), k, f) == k; }
+    template <typename T> bool get(T* v, size_t k) { return fread(v, sizeof(T), k, f) == k; }
+};
+
+// Positions [n][3] of the image of the given parity.
+int read_image(mc_handle* h, const Chain& c, int parity, double* xyz) {
+    if (h->fp64) {
+        std::vector<double4> v(c.n);
+        HIPCHECK(h, hipMemcpy(v.data(), (double4*)c.pos + (size_t)parity * c.npad, sizeof(double4) * c.n,
+                              hipMemcpyDeviceToHost));
+        for (int i = 0; i < c.n; ++i) {
+            xyz[3 * i] = v[i].x;
+            xyz[3 * i + 1] = v[i].y;
+            xyz[3 * i + 2] = v[i].z;
+        }
+    } else {
+        std::vector<float4> v(c.n);
+        HIPCHECK(h, hipMemcpy(v.data(), (float4*)c.pos + (size_t)parity * c.npad, sizeof(float4) * c.n,
+                              hipMemcpyDeviceToHost));
+        for (int i = 0; i < c.n; ++i) {
+            xyz[3 * i] = v[i].x;
+            xyz[3 * i + 1] = v[i].y;
+            xyz[3 * i + 2] = v[i].z;
+        }
+    }
+    return MC_OK;
+}
+
+// Writes both position images and the group-record ring as a finished sweep
+// s0 - 1 leaves them: the image of sweep s0 - 1 holds xyz, that of sweep
+// s0 - 2 holds prev, and the last kRing groups before sweep s0 are decided
+// with the accept masks given (oldest first; all rejected when masks is
+// NULL).  Every reader then sees the state exactly as the sweep kernel
+// wrote it.
+int write_start(mc_handle* h, Chain& c, const double* xyz, const double* prev, const uint64_t* masks,
+                int64_t s0) {
+    const size_t t4 = h->fp64 ? sizeof(double4) : sizeof(float4);
+    std::vector<char> img(2 * t4 * c.npad);
+    HIPCHECK(h, hipMemcpy(img.data(), c.pos, img.size(), hipMemcpyDeviceToHost));
+    for (int par = 0; par < 2; ++par) {
+        // parity (s0 - 1) & 1 holds sweep s0 - 1, the other one sweep s0 - 2
+        const bool last = par == ((s0 - 1) & 1);
+        const uint32_t ver = (uint32_t)(last ? s0 - 1 : s0 - 2);
+        const double* src = last ? xyz : prev;
+        for (int i = 0; i < c.npad; ++i) {
+            char* dst = &img[t4 * ((size_t)par * c.npad + i)];
+            if (h->fp64) {
+                struct { double x, y, z; uint32_t ver, pad; } r;
+                std::memcpy(&r, dst, t4);
+                if (i < c.n) {
+                    r.x = src[3 * i];
+                    r.y = src[3 * i + 1];
+                    r.z = src[3 * i + 2];
+                }
+                r.ver = ver;
+                std::memcpy(dst, &r, t4);
+            } else {
+                struct { float x, y, z; uint32_t ver; } r;
+                std::memcpy(&r, dst, t4);
+                if (i < c.n) {
+                    r.x = (float)src[3 * i];
+                    r.y = (float)src[3 * i + 1];
+                    r.z = (float)src[3 * i + 2];
+                }
+                r.ver = ver;
+                std::memcpy(dst, &r, t4);
+            }
+        }
+    }
+    HIPCHECK(h, hipMemcpy(c.pos, img.data(), img.size(), hipMemcpyHostToDevice));
+    std::vector<GroupRec> ring(kRing);
+    const int64_t g0 = s0 * (int64_t)c.nb;
+    for (int q = 0; q < kRing; ++q) {
+        const int64_t g = g0 - kRing + q;
+        ring[(size_t)(g & (kRing - 1))] = GroupRec{(uint32_t)(g + 1), 0u, masks ? masks[q] : 0ull};
+    }
+    HIPCHECK(h, hipMemcpy(c.rec, ring.data(), sizeof(GroupRec) * kRing, hipMemcpyHostToDevice));
+    return MC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int mc_options_init(mc_options* o) {
@@ -1315,6 +1431,193 @@ int mc_create_batch(int32_t n_chains, const mc_chain_spec* chains, const mc_opti
     for (int k = 0; k < n_chains; ++k)
         if ((rc = validate_chain(chains[k], opt, "chain " + std::to_string(k) + ": "))) return rc;
     return create_handle(n_chains, chains, opt, out);
+}
+
+int mc_save(mc_handle* h, const char* path) {
+    if (!h) return MC_E_ARG;
+    if (!path) return fail(h, MC_E_ARG, "path is NULL");
+    int rc = sync_check(h);
+    if (rc) return rc;
+    std::vector<CkptChain> cs(h->chains.size());
+    for (size_t k = 0; k < h->chains.size(); ++k) {
+        Chain& c = h->chains[k];
+        CkptChain& o = cs[k];
+        o.n = c.n;
+        o.nt = (int32_t)c.species.size();
+        o.bins = h->opt.rdf_bins;
+        o.chain_id = c.chain_id;
+        o.R = c.R;
+        o.lB = c.lB;
+        o.max_disp = 0.5 * c.D;
+        o.q.resize(c.n);
+        o.sigma.resize(c.n);
+        for (int i = 0; i < c.n; ++i) {
+            o.q[i] = c.species[(size_t)c.type[i]].first;
+            o.sigma[i] = c.species[(size_t)c.type[i]].second;
+        }
+        o.xyz.resize(3 * (size_t)c.n);
+        o.prev.resize(3 * (size_t)c.n);
+        if ((rc = read_image(h, c, (int)((h->sweeps - 1) & 1), o.xyz.data())) ||
+            (rc = read_image(h, c, (int)(h->sweeps & 1), o.prev.data())))
+            return rc;
+        std::vector<GroupRec> ring(kRing);
+        HIPCHECK(h, hipMemcpy(ring.data(), c.rec, sizeof(GroupRec) * kRing, hipMemcpyDeviceToHost));
+        o.masks.resize(kRing);
+        const int64_t g0 = h->sweeps * (int64_t)c.nb;
+        for (int q = 0; q < kRing; ++q) {
+            const int64_t g = g0 - kRing + q;
+            const GroupRec& r = ring[(size_t)(g & (kRing - 1))];
+            if (r.tag != (uint32_t)(g + 1)) return fail(h, MC_E_STATE, "group record ring out of step");
+            o.masks[q] = r.acc;
+        }
+        HIPCHECK(h, hipMemcpy(&o.e_run, c.e_state, sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHECK(h, hipMemcpy(&o.aux, c.aux, sizeof(EnergyAux), hipMemcpyDeviceToHost));
+        HIPCHECK(h, hipMemcpy(o.stats, c.stats, sizeof(o.stats), hipMemcpyDeviceToHost));
+        o.counts.resize((size_t)o.nt * o.nt * o.bins);
+        o.centres.resize((size_t)o.nt);
+        HIPCHECK(h, hipMemcpy(o.counts.data(), c.rdf_counts, sizeof(unsigned long long) * o.counts.size(),
+                              hipMemcpyDeviceToHost));
+        HIPCHECK(h, hipMemcpy(o.centres.data(), c.rdf_centres, sizeof(unsigned long long) * o.centres.size(),
+                              hipMemcpyDeviceToHost));
+        o.series.resize((size_t)std::min<int64_t>(h->sweeps, c.e_capacity));
+        if (!o.series.empty())
+            HIPCHECK(h, hipMemcpy(o.series.data(), c.e_series, sizeof(double) * o.series.size(),
+                                  hipMemcpyDeviceToHost));
+    }
+    File f(fopen(path, "wb"));
+    if (!f.f) return fail(h, MC_E_ARG, std::string("cannot open ") + path + " for writing");
+    mc_options opt = h->opt;
+    opt.hip_stream = nullptr;
+    const int32_t hdr[4] = {kCkptVersion, (int32_t)cs.size(), (int32_t)sizeof(mc_options), (int32_t)ST_N};
+    const int64_t cnt[2] = {h->sweeps, h->rdf_samples};
+    bool ok = f.put(kCkptMagic, 8) && f.put(hdr, 4) && f.put(cnt, 2) && f.put(&opt, 1);
+    for (const CkptChain& o : cs) {
+        const int32_t ci[4] = {o.n, o.nt, o.bins, (int32_t)o.chain_id};
+        const double cd[4] = {o.R, o.lB, o.max_disp, o.e_run};
+        const int64_t m = (int64_t)o.series.size();
+        ok = ok && f.put(ci, 4) && f.put(cd, 4) && f.put(&o.aux, 1) && f.put(o.stats, ST_N) &&
+             f.put(o.q.data(), o.q.size()) && f.put(o.sigma.data(), o.sigma.size()) &&
+             f.put(o.xyz.data(), o.xyz.size()) && f.put(o.prev.data(), o.prev.size()) &&
+             f.put(o.masks.data(), o.masks.size()) && f.put(o.counts.data(), o.counts.size()) &&
+             f.put(o.centres.data(), o.centres.size()) && f.put(&m, 1) &&
+             (m == 0 || f.put(o.series.data(), o.series.size()));
+    }
+    if (!ok || fflush(f.f) != 0) return fail(h, MC_E_ARG, std::string("writing ") + path + " failed");
+    return MC_OK;
+}
+
+int mc_load(const char* path, const mc_options* opt_in, mc_handle** out) {
+    if (!out) return fail(nullptr, MC_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!path) return fail(nullptr, MC_E_ARG, "path is NULL");
+    File f(fopen(path, "rb"));
+    if (!f.f) return fail(nullptr, MC_E_ARG, std::string("cannot open ") + path);
+    const std::string bad = std::string(path) + " is not a checkpoint of this library version";
+    char magic[8];
+    int32_t hdr[4];
+    int64_t cnt[2];
+    mc_options saved;
+    if (!f.get(magic, 8) || std::memcmp(magic, kCkptMagic, 8) != 0 || !f.get(hdr, 4) || hdr[0] != kCkptVersion ||
+        hdr[1] < 1 || hdr[2] != (int32_t)sizeof(mc_options) || hdr[3] != (int32_t)ST_N || !f.get(cnt, 2) ||
+        cnt[0] < 0 || cnt[0] > (int64_t)UINT32_MAX || cnt[1] < 0 || !f.get(&saved, 1))
+        return fail(nullptr, MC_E_ARG, bad);
+    saved.hip_stream = nullptr;
+    mc_options opt = saved;
+    if (opt_in) {
+        opt = *opt_in;
+        if (opt.precision != saved.precision || opt.rdf_bins != saved.rdf_bins)
+            return fail(nullptr, MC_E_ARG, "precision and rdf_bins must be those of the checkpoint");
+    }
+    int rc = check_options(opt);
+    if (rc) return rc;
+    std::vector<CkptChain> cs((size_t)hdr[1]);
+    for (CkptChain& o : cs) {
+        int32_t ci[4];
+        double cd[4];
+        if (!f.get(ci, 4) || !f.get(cd, 4) || ci[0] < 1 || ci[0] > (1 << 24) || ci[1] < 1 || ci[1] > 8 ||
+            ci[2] != saved.rdf_bins)
+            return fail(nullptr, MC_E_ARG, bad);
+        o.n = ci[0];
+        o.nt = ci[1];
+        o.bins = ci[2];
+        o.chain_id = (uint32_t)ci[3];
+        o.R = cd[0];
+        o.lB = cd[1];
+        o.max_disp = cd[2];
+        o.e_run = cd[3];
+        o.q.resize(o.n);
+        o.sigma.resize(o.n);
+        o.xyz.resize(3 * (size_t)o.n);
+        o.prev.resize(3 * (size_t)o.n);
+        o.masks.resize(kRing);
+        o.counts.resize((size_t)o.nt * o.nt * o.bins);
+        o.centres.resize((size_t)o.nt);
+        int64_t m = 0;
+        if (!f.get(&o.aux, 1) || !f.get(o.stats, ST_N) || !f.get(o.q.data(), o.q.size()) ||
+            !f.get(o.sigma.data(), o.sigma.size()) || !f.get(o.xyz.data(), o.xyz.size()) ||
+            !f.get(o.prev.data(), o.prev.size()) || !f.get(o.masks.data(), o.masks.size()) ||
+            !f.get(o.counts.data(), o.counts.size()) || !f.get(o.centres.data(), o.centres.size()) ||
+            !f.get(&m, 1) || m < 0 || m > cnt[0])
+            return fail(nullptr, MC_E_ARG, bad);
+        o.series.resize((size_t)m);
+        if (m > 0 && !f.get(o.series.data(), o.series.size())) return fail(nullptr, MC_E_ARG, bad);
+    }
+    std::vector<mc_chain_spec> specs(cs.size());
+    for (size_t k = 0; k < cs.size(); ++k) {
+        mc_chain_spec& sp = specs[k];
+        std::memset(&sp, 0, sizeof(sp));
+        sp.n = cs[k].n;
+        sp.charges = cs[k].q.data();
+        sp.diameters = cs[k].sigma.data();
+        sp.positions = cs[k].xyz.data();
+        sp.radius = cs[k].R;
+        sp.l_B = cs[k].lB;
+        sp.max_disp = cs[k].max_disp;
+        sp.chain_id = cs[k].chain_id;
+        if ((rc = validate_chain(sp, opt, "chain " + std::to_string(k) + ": ", false))) return rc;
+    }
+    mc_handle* h = nullptr;
+    if ((rc = create_handle((int32_t)specs.size(), specs.data(), opt, &h))) return rc;
+    auto bail = [&](int code) {
+        g_create_error = h->err;
+        mc_destroy(h);
+        return code;
+    };
+    h->sweeps = cnt[0];
+    h->rdf_samples = cnt[1];
+    for (size_t k = 0; k < cs.size(); ++k) {
+        Chain& c = h->chains[k];
+        const CkptChain& o = cs[k];
+        if (c.species.size() != (size_t)o.nt) {
+            h->err = bad;
+            return bail(MC_E_ARG);
+        }
+        for (double v : o.prev)
+            if (!is_finite(v)) {
+                h->err = bad;
+                return bail(MC_E_ARG);
+            }
+        if ((rc = write_start(h, c, o.xyz.data(), o.prev.data(), o.masks.data(), h->sweeps))) return bail(rc);
+        if ((rc = grow_buffer(h, &c.e_series, &c.e_capacity, std::max<int64_t>(1024, h->sweeps), true)))
+            return bail(rc);
+        hipError_t e = hipSuccess;
+        if ((e = hipMemcpy(c.e_state, &o.e_run, sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c.aux, &o.aux, sizeof(EnergyAux), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c.stats, o.stats, sizeof(o.stats), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c.rdf_counts, o.counts.data(), sizeof(unsigned long long) * o.counts.size(),
+                           hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c.rdf_centres, o.centres.data(), sizeof(unsigned long long) * o.centres.size(),
+                           hipMemcpyHostToDevice)) != hipSuccess ||
+            (!o.series.empty() && (e = hipMemcpy(c.e_series, o.series.data(), sizeof(double) * o.series.size(),
+                                                 hipMemcpyHostToDevice)) != hipSuccess)) {
+            h->err = std::string("upload failed: ") + hipGetErrorString(e);
+            return bail(MC_E_DEVICE);
+        }
+    }
+    if ((rc = upload_desc(h))) return bail(rc);
+    if ((rc = sync_check(h))) return bail(rc);
+    *out = h;
+    return MC_OK;
 }
 
 int mc_sweep(mc_handle* h, int64_t n_sweeps, uint64_t seed) {

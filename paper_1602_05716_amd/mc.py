@@ -71,7 +71,7 @@ class ChainSpec(ctypes.Structure):
 
 # Every symbol include/mc.h declares.
 SYMBOLS = ["mc_options_init", "mc_create", "mc_sweep", "mc_sweep_reduction", "mc_energy", "mc_rdf", "mc_rdf_sample",
-           "mc_rdf_reset", "mc_species", "mc_get_positions", "mc_trace", "mc_energy_series",
+           "mc_rdf_reset", "mc_save", "mc_load", "mc_species", "mc_get_positions", "mc_trace", "mc_energy_series",
            "mc_get_stats", "mc_timing", "mc_timing_reset", "mc_set_max_disp",
            "mc_create_batch", "mc_chain_count", "mc_chain_energy", "mc_chain_rdf", "mc_chain_species",
            "mc_chain_positions", "mc_chain_trace", "mc_chain_energy_series", "mc_chain_stats",
@@ -103,6 +103,8 @@ def load(path: str = LIB_PATH):
         "mc_rdf": ([_hp, ctypes.c_int32, _f64p, _u64p, _u64p, _i64p], ctypes.c_int),
         "mc_rdf_sample": ([_hp], ctypes.c_int),
         "mc_rdf_reset": ([_hp], ctypes.c_int),
+        "mc_save": ([_hp, ctypes.c_char_p], ctypes.c_int),
+        "mc_load": ([ctypes.c_char_p, ctypes.POINTER(Options), ctypes.POINTER(_hp)], ctypes.c_int),
         "mc_species": ([_hp, _i32p, _f64p, _f64p], ctypes.c_int),
         "mc_get_positions": ([_hp, _f64p], ctypes.c_int),
         "mc_trace": ([_hp, ctypes.c_int64, _u8p, _f64p], ctypes.c_int),
@@ -167,6 +169,30 @@ def _p(a, t):
     return a.ctypes.data_as(t)
 
 
+RING = 1024  # group records kept per chain (accept masks in a checkpoint)
+
+
+def _checkpoint_header(path):
+    """(saved options, ion count per chain) from a checkpoint written by mc_save."""
+    with open(path, "rb") as f:
+        head = f.read(8 + 16 + 16 + ctypes.sizeof(Options))
+        if len(head) < 40 + ctypes.sizeof(Options) or head[:8] != b"MCCKPT01":
+            raise MCError(-1, "%s is not a checkpoint" % path)
+        hdr = np.frombuffer(head[8:24], np.int32)  # version, chains, sizeof(options), counters
+        n_chains, n_counters = int(hdr[1]), int(hdr[3])
+        saved = Options.from_buffer_copy(head[40:])
+        ns = []
+        for _ in range(n_chains):
+            ci = np.frombuffer(f.read(16), np.int32)
+            ns.append(int(ci[0]))
+            nt, bins = int(ci[1]), int(ci[2])
+            f.read(32 + 32 + 8 * n_counters)  # R, l_B, max_disp, energy; re-sum record; counters
+            f.seek(8 * (8 * ns[-1] + RING + nt * nt * bins + nt), 1)
+            m = int(np.frombuffer(f.read(8), np.int64)[0])
+            f.seek(8 * m, 1)
+    return saved, ns
+
+
 class Chain:
     """One Markov chain living on the GPU (a handle of the C ABI)."""
 
@@ -195,6 +221,27 @@ class Chain:
     def sweep_reduction(self, n_sweeps, seed):
         """The same sweeps by the per-move parallel-reduction scheme (mc_sweep_reduction)."""
         self._check(self._L.mc_sweep_reduction(self.h, int(n_sweeps), int(seed)))
+
+    def save(self, path):
+        """Checkpoint of the chain (mc_save)."""
+        self._check(self._L.mc_save(self.h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path, **opts):
+        """A chain resumed from a checkpoint (mc_load); no options: the saved ones."""
+        saved, ns = _checkpoint_header(path)
+        if len(ns) != 1:
+            raise MCError(-1, "the checkpoint holds %d chains (use Batch.load)" % len(ns))
+        self = cls.__new__(cls)
+        self._L = lib()
+        self.opt = options(**opts) if opts else saved
+        self.n = ns[0]
+        h = _hp()
+        rc = self._L.mc_load(os.fsencode(path), ctypes.byref(self.opt) if opts else None, ctypes.byref(h))
+        if rc != MC_OK:
+            raise MCError(rc, self._L.mc_last_error(None).decode())
+        self.h = h
+        return self
 
     def energy(self, exact=False):
         er = ctypes.c_double()
@@ -380,6 +427,26 @@ class Batch:
         st = Stats()
         self._check(self._L.mc_chain_stats(self.h, int(c), ctypes.byref(st)))
         return st.as_dict()
+
+    def save(self, path):
+        """Checkpoint of every chain (mc_save)."""
+        self._check(self._L.mc_save(self.h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path, **opts):
+        """A batch resumed from a checkpoint (mc_load); no options: the saved ones."""
+        saved, ns = _checkpoint_header(path)
+        self = cls.__new__(cls)
+        self._L = lib()
+        self._keep = []
+        self.opt = options(**opts) if opts else saved
+        self.n = ns
+        h = _hp()
+        rc = self._L.mc_load(os.fsencode(path), ctypes.byref(self.opt) if opts else None, ctypes.byref(h))
+        if rc != MC_OK:
+            raise MCError(rc, self._L.mc_last_error(None).decode())
+        self.h = h
+        return self
 
     def set_max_disp(self, c, v):
         self._check(self._L.mc_chain_set_max_disp(self.h, int(c), float(v)))

@@ -34,6 +34,20 @@ def test_null_handles_are_rejected():
     assert L.mc_sweep_reduction(None, 1, 1) == -1
 
 
+def test_checkpoint_entry_points_reject_bad_input(tmp_path):
+    """Host-side checks of mc_save / mc_load (no device work)."""
+    from paper_1602_05716_amd import mc
+    L = mc.lib()
+    h = ctypes.c_void_p()
+    assert L.mc_save(None, b"x") == -1
+    assert L.mc_load(None, None, ctypes.byref(h)) == -1 and not h.value
+    assert L.mc_load(str(tmp_path / "missing").encode(), None, ctypes.byref(h)) == -1 and not h.value
+    junk = tmp_path / "junk.ckpt"
+    junk.write_bytes(b"MCCKPT01" + b"\x00" * 64)
+    assert L.mc_load(str(junk).encode(), None, ctypes.byref(h)) == -1 and not h.value
+    assert "checkpoint" in L.mc_last_error(None).decode()
+
+
 def test_options_defaults():
     from paper_1602_05716_amd import mc
     o = mc.options()

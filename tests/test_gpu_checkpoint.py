@@ -1,0 +1,87 @@
+"""Checkpoint and resume through the C ABI (mc_save / mc_load).
+
+The random stream is a function of (seed, sweep, ion, chain), so a chain
+saved after k sweeps, loaded and run on must reproduce the uninterrupted
+chain bit for bit: decisions, positions, the running energy, the energy
+series, the re-sum record, the counters and the g(r) counts.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _sys(n_cat, n_an, q=(1.0, -1.0), s=(1.0, 1.0), phi=0.05, lB=0.7, seed=1):
+    from paper_1602_05716_amd import inputs
+    sy = inputs.electrolyte(n_cat, n_an, q[0], q[1], s[0], s[1], phi, lB)
+    sy.xyz = inputs.random_start(sy, seed)
+    return sy
+
+
+KEYS = ("sweeps", "moves", "accepted", "rejected_wall", "rejected_overlap", "rejected_metropolis", "resums",
+        "last_drift", "max_abs_drift")
+
+
+def _state(ch, sweeps, n):
+    acc, de = ch.trace(sweeps * n)
+    st = ch.stats()
+    r = ch.rdf()
+    return dict(x=ch.positions(), e=ch.energy(), es=ch.energy_series(sweeps), acc=acc, de=de,
+                st={k: st[k] for k in KEYS}, counts=r["counts"], centres=r["centres"], samples=r["samples"])
+
+
+@pytest.mark.parametrize("precision,opts", [("fp64", {}), ("fp32", dict(band=4, waves=8)),
+                                            ("fp32", dict(band=2))])
+def test_resume_is_bit_exact(tmp_path, precision, opts):
+    from paper_1602_05716_amd import mc
+    sy = _sys(350, 350, q=(1.0, -1.0), seed=21)
+    total, cut, seed = 10, 6, 77
+    kw = dict(precision=precision, max_disp=0.7, resum_every=4, rdf_every=3, rdf_bins=40, rdf_rmax=4.0,
+              trace_moves=total * sy.n, **opts)
+    _say("resume %s N=%d opts=%s" % (precision, sy.n, opts))
+    with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, **kw) as a:
+        a.sweep(total, seed)
+        ref = _state(a, total, sy.n)
+    path = str(tmp_path / "chain.ckpt")
+    with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, **kw) as b:
+        b.sweep(cut, seed)
+        b.save(path)
+    with mc.Chain.load(path) as c:  # the saved options
+        assert c.stats()["sweeps"] == cut
+        c.sweep(total - cut, seed)
+        got = _state(c, total, sy.n)
+    assert np.array_equal(got["x"], ref["x"])
+    assert got["e"] == ref["e"]
+    assert np.array_equal(got["es"], ref["es"])
+    m = slice(cut * sy.n, total * sy.n)  # traced after the load
+    assert np.array_equal(got["acc"][m], ref["acc"][m]) and np.array_equal(got["de"][m], ref["de"][m])
+    assert got["st"] == ref["st"]
+    assert got["samples"] == ref["samples"] == 3
+    assert np.array_equal(got["counts"], ref["counts"]) and np.array_equal(got["centres"], ref["centres"])
+
+
+def test_batch_resume_and_options(tmp_path):
+    from paper_1602_05716_amd import mc
+    systems = [_sys(100 + 37 * k, 100 + 37 * k, seed=40 + k) for k in range(3)]
+    kw = dict(precision="fp32", resum_every=5)
+    _say("batch resume 3 chains")
+    with mc.Batch(systems, max_disp=[0.4, 0.6, 0.8], **kw) as a:
+        a.sweep(9, 5)
+        ref = [a.positions(k) for k in range(3)]
+        ea = [a.energy(k) for k in range(3)]
+    path = str(tmp_path / "batch.ckpt")
+    with mc.Batch(systems, max_disp=[0.4, 0.6, 0.8], **kw) as b:
+        b.sweep(4, 5)
+        b.save(path)
+    # options given on load: same precision and g(r) bins, a different schedule
+    with mc.Batch.load(path, precision="fp32", resum_every=5, workgroups=3) as c:
+        c.sweep(5, 5)
+        for k in range(3):
+            assert np.array_equal(c.positions(k), ref[k])
+            assert abs(c.energy(k) - ea[k]) <= 1e-9 * max(1.0, abs(ea[k]))
+    with pytest.raises(mc.MCError):
+        mc.Batch.load(path, precision="fp64")
