@@ -264,7 +264,9 @@ def da_leg(args, md):
         with mc.Chain(x0, system.q, system.sigma, system.R, system.lB, **kw) as c:
             if mode == "da":
                 c.set_surrogate(tr["params"], tr["ref_stage2_reject"], True)
-            c.sweep(2, seed + 1)  # first launch out of the timed region
+            # first launch out of the timed region; one drift-monitor window
+            # (10 sweeps), so that every timed call below is a single launch
+            c.sweep(10, seed + 1)
             t, e, halves = _gr_sample_run(c, args.da_sweeps, seed + 2, 10)
             st = c.stats()
             ess = analysis.effective_samples(e)
