@@ -37,11 +37,11 @@ def _log(*a):
 
 
 def run(n: int, sweeps: int, equil: int, every: int, rmax: float, bins: int, seed: int, chunk: int = 100,
-        margin: float | None = None):
+        margin: float | None = None, debye_A: float = inputs.PAPER_DEBYE_A):
     import torch
     from . import mc
     t0 = time.perf_counter()
-    sy = inputs.three_to_one(n, seed)
+    sy = inputs.three_to_one(n, seed, debye_A)
     _log("start built: N=%d R=%.2f (%.1f s)" % (n, sy.R, time.perf_counter() - t0))
     md = sy.R / 3.0  # cube side 2 md = L / 3
     if margin is None:  # every neighbour counted at least ten bare Debye lengths inside the wall
@@ -77,11 +77,15 @@ def run(n: int, sweeps: int, equil: int, every: int, rmax: float, bins: int, see
     return sy, md, r, st, es, wall, n_of_type, (e_run, e_ex), margin
 
 
-def analyse(r_c, g, n_of_type, R, fit, r_flat=None):
+def analyse(r_c, g, n_of_type, R, fit, r_flat=None, counts=None):
+    """Dressed-ion parameters of one run (or of pooled counts); with the raw
+    counts the fit is weighted by their Poisson errors."""
     vb = 4.0 / 3.0 * np.pi * (R - 0.5) ** 3
     n = n_of_type / vb
-    res = analysis.renormalised_parameters(r_c, g, n, [3.0, -1.0], inputs.PAPER_BJERRUM_A / inputs.PAPER_DIAMETER_A,
-                                           fit=fit, r_flat=r_flat)
+    q = [3.0, -1.0]
+    err = None if counts is None else analysis.charge_density_error(counts, g, n, q)
+    res = analysis.renormalised_parameters(r_c, g, n, q, inputs.PAPER_BJERRUM_A / inputs.PAPER_DIAMETER_A,
+                                           fit=fit, r_flat=r_flat, rho_err=err)
     d = inputs.PAPER_DIAMETER_A
     out = {k: v for k, v in res.items() if k not in ("rho", "U")}
     out.update({"fit_window_sigma": list(fit), "kappa_inv_A": d / res["kappa"], "kappa_R_inv_A": d / res["kappa_R"],
@@ -103,7 +107,7 @@ def pooled(paths, fit, r_flat=None) -> dict:
     centres = sum(d["centres"].astype(np.float64) for d in runs)
     R, rmax = float(ref["R"]), float(ref["rmax"])
     r_c, g = analysis.g_from_counts(counts, centres, ref["n_of_type"], [1.0, 1.0], R, rmax)
-    out = analyse(r_c, g, ref["n_of_type"], R, fit, r_flat)
+    out = analyse(r_c, g, ref["n_of_type"], R, fit, r_flat, counts=counts)
     out.update({"runs": len(runs), "samples": int(sum(int(d["samples"]) for d in runs)),
                 "tau_int_sweeps": [analysis.integrated_time(d["energy"]) for d in runs]})
     return out
@@ -115,34 +119,44 @@ def main():
     ap.add_argument("--sweeps", type=int, default=1000)
     ap.add_argument("--equil", type=int, default=100)
     ap.add_argument("--every", type=int, default=10)
-    ap.add_argument("--rmax", type=float, default=40.0, help="g(r) range (diameters)")
+    ap.add_argument("--debye-A", type=float, default=inputs.PAPER_DEBYE_A,
+                    help="bare Debye length in Angstrom (sets the density)")
+    ap.add_argument("--rmax", type=float, default=0.0,
+                    help="g(r) range in diameters (0: 10.5 bare Debye lengths)")
     ap.add_argument("--bins", type=int, default=400)
     ap.add_argument("--seed", type=int, default=0x5EED0007)
     ap.add_argument("--chunk", type=int, default=100, help="sweeps per call (progress lines)")
-    ap.add_argument("--fit", type=float, nargs=2, default=[8.0, 16.0], help="far-field window (diameters)")
+    ap.add_argument("--fit", type=float, nargs=2, default=[0.0, 0.0],
+                    help="far-field window in diameters (0 0: 4.2 to 7.9 bare Debye lengths)")
     ap.add_argument("--out", default="")
     ap.add_argument("--pool", nargs="+", default=None,
                     help="analysis only (no GPU): pool the counts of these saved runs of one system")
     a = ap.parse_args()
+    lam = a.debye_A / inputs.PAPER_DIAMETER_A  # bare Debye length in diameters
+    if a.rmax <= 0:
+        a.rmax = round(10.5 * lam, 1)
+    if a.fit[1] <= 0:
+        a.fit = [round(4.2 * lam, 1), round(7.9 * lam, 1)]
     if a.pool:
         print(json.dumps(pooled(a.pool, tuple(a.fit))), flush=True)
         return
     sy, md, r, st, es, wall, n_of_type, (e_run, e_ex), margin = run(a.n, a.sweeps, a.equil, a.every, a.rmax, a.bins, a.seed,
-                                                             a.chunk)
+                                                             a.chunk, debye_A=a.debye_A)
     dr = a.rmax / a.bins
     r_c = (np.arange(a.bins) + 0.5) * dr
     if a.out:
         np.savez(a.out, counts=r["counts"], centres=r["centres"], samples=r["samples"], g=r["g"],
                  n_of_type=n_of_type, R=sy.R, rmax=a.rmax, bins=a.bins, energy=es, max_disp=md, n=a.n,
-                 margin=margin)
+                 margin=margin, debye_A=a.debye_A)
     tau = analysis.integrated_time(es) if len(es) > 8 else float("nan")
-    out = {"n": a.n, "R": sy.R, "max_disp": md, "rdf_margin": margin, "sweeps": a.sweeps, "equil": a.equil, "every": a.every,
+    out = {"n": a.n, "debye_A": a.debye_A, "R": sy.R, "max_disp": md, "rdf_margin": margin, "rmax": a.rmax,
+           "sweeps": a.sweeps, "equil": a.equil, "every": a.every,
            "samples": r["samples"], "wall_s": wall, "ms_per_sweep": 1e3 * wall / max(1, a.sweeps),
            "acceptance": st["accepted"] / max(1, st["moves"]), "tau_int_sweeps": tau,
            "paper_tau_int": PAPER_TAU_INT, "e_running": e_run, "e_resum": e_ex,
            "rejected_wall": st["rejected_wall"], "rejected_overlap": st["rejected_overlap"]}
     try:
-        out["dressed"] = analyse(r_c, r["g"], n_of_type, sy.R, tuple(a.fit))
+        out["dressed"] = analyse(r_c, r["g"], n_of_type, sy.R, tuple(a.fit), counts=r["counts"])
     except ValueError as e:  # a noisy window: the raw counts are saved for another fit
         out["dressed_error"] = str(e)
     print(json.dumps(out), flush=True)

@@ -183,24 +183,26 @@ PAPER_BJERRUM_A = 7.117
 PAPER_DEBYE_A = 28.53
 
 
-def three_to_one_density() -> tuple[float, float]:
-    """(n_+, n_-) in ions per diameter^3 of the paper's 3:-1 system."""
+def three_to_one_density(debye_A: float = PAPER_DEBYE_A) -> tuple[float, float]:
+    """(n_+, n_-) in ions per diameter^3 of the paper's 3:-1 electrolyte at the
+    bare Debye length debye_A (Angstrom; 28.53 is the paper's system)."""
     lB = PAPER_BJERRUM_A / PAPER_DIAMETER_A
-    kappa = PAPER_DIAMETER_A / PAPER_DEBYE_A
+    kappa = PAPER_DIAMETER_A / debye_A
     n_plus = kappa * kappa / (4.0 * np.pi * lB * (9.0 + 3.0))
     return n_plus, 3.0 * n_plus
 
 
-def three_to_one(n: int = 1 << 20, seed: int = 0x5EED0007) -> System:
+def three_to_one(n: int = 1 << 20, seed: int = 0x5EED0007, debye_A: float = PAPER_DEBYE_A) -> System:
     """The paper's 3:-1 system with n ions (n / 4 at +3, 3 n / 4 at -1, all
-    of diameter 1 = 7.5 A), at its density (phi = (n_+ + n_-) pi / 6, about
-    1.0e-3), in a hard-wall sphere; uniform random start without overlap."""
+    of diameter 1 = 7.5 A), at the density of bare Debye length debye_A
+    (the paper's 28.53 A: phi = (n_+ + n_-) pi / 6, about 1.0e-3), in a
+    hard-wall sphere; uniform random start without overlap."""
     if n % 4:
         raise ValueError("n must be a multiple of 4")
-    n_plus, n_minus = three_to_one_density()
+    n_plus, n_minus = three_to_one_density(debye_A)
     phi = (n_plus + n_minus) * np.pi / 6.0
     s = electrolyte(n // 4, 3 * n // 4, 3.0, -1.0, 1.0, 1.0, phi, PAPER_BJERRUM_A / PAPER_DIAMETER_A,
-                    name=f"3:-1 N={n} (paper's production system, diameter 7.5 A)")
+                    name=f"3:-1 N={n}, bare Debye length {debye_A} A (diameter 7.5 A)")
     s.xyz = random_start(s, seed)
-    s.meta.update(seed=seed, kappa_inv=PAPER_DEBYE_A / PAPER_DIAMETER_A, phi=phi)
+    s.meta.update(seed=seed, kappa_inv=debye_A / PAPER_DIAMETER_A, phi=phi, debye_A=debye_A)
     return s
