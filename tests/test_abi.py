@@ -86,6 +86,11 @@ def test_create_rejects_wall_crossing():
     assert rc != -3
 
 
+def test_create_rejects_bad_rdf_margin():
+    rc, msg = _create(2, [1.0, -1.0], [1.0, 1.0], [[0, 0, 0], [3, 0, 0]], rdf_margin=-1.0)
+    assert rc == -1 and "rdf_margin" in msg, msg
+
+
 def test_create_rejects_overlap():
     rc, msg = _create(3, [1.0, -1.0, 0.0], [1.0, 0.5, 1.0], [[0, 0, 0], [0.74, 0, 0], [5, 0, 0]])
     assert rc == -2, msg

@@ -85,3 +85,22 @@ def test_batch_resume_and_options(tmp_path):
             assert abs(c.energy(k) - ea[k]) <= 1e-9 * max(1.0, abs(ea[k]))
     with pytest.raises(mc.MCError):
         mc.Batch.load(path, precision="fp64")
+
+
+def test_production_driver_runs_and_pools(tmp_path):
+    """The 3:-1 production driver end to end at a small size (no physics
+    assertion: a few sweeps carry no far-field signal): counts saved, pooled,
+    and the pooled g equal to the library's own for one run."""
+    from paper_1602_05716_amd import analysis, dressed
+    _say("dressed driver N=4096")
+    sy, md, r, st, es, wall, n_of_type, (e_run, e_ex), margin = dressed.run(
+        4096, 6, 2, 2, 12.0, 60, 9, chunk=3, debye_A=20.0)
+    assert r["samples"] == 3 and st["sweeps"] == 8 and len(es) == 6
+    assert abs(e_run - e_ex) <= 1e-6 * max(1.0, abs(e_ex))
+    path = str(tmp_path / "d.npz")
+    np.savez(path, counts=r["counts"], centres=r["centres"], samples=r["samples"], g=r["g"], n_of_type=n_of_type,
+             R=sy.R, rmax=12.0, bins=60, energy=es, max_disp=md, n=4096, margin=margin)
+    rc, g = analysis.g_from_counts(r["counts"], r["centres"], n_of_type, [1.0, 1.0], sy.R, 12.0)
+    assert np.allclose(g, r["g"], rtol=1e-12, atol=0)
+    with pytest.raises(ValueError):
+        dressed.pooled([path, path], (5.0, 5.1))  # too few bins in the window
