@@ -31,9 +31,8 @@ def _tune(ch, md, rounds=6, sweeps=2, target=0.40, seed=0xD15C):
 
 
 def _timed(ch, fn, sweeps, seed):
-    import torch
     ch.timing_reset()
-    torch.cuda.synchronize()
+    ch.energy()  # synchronises the chain's stream
     t0 = time.perf_counter()
     fn(sweeps, seed)
     ch.energy()  # synchronises the chain's stream
@@ -43,15 +42,13 @@ def _timed(ch, fn, sweeps, seed):
 
 
 def measure(n: int, sweeps: int = 0, reduction_sweeps: int = 1, seed: int = 0x5EED0006) -> dict:
-    import torch
     from . import inputs, mc
     sy = inputs.electrolyte(n // 2, n - n // 2, 1.0, -1.0, 1.0, 1.0, 0.05, 0.7)
     sy.xyz = inputs.random_start(sy, seed)
     if sweeps <= 0:  # about 2e11 pair terms, at least 2 sweeps
         sweeps = max(2, int(2e11 / (n * (n - 1.0))))
-    stream = torch.cuda.Stream()
     with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision="fp32", max_disp=0.5, resum_every=0,
-                  record_timing=1, hip_stream=stream.cuda_stream) as ch:
+                  record_timing=1) as ch:  # the handle's own stream
         md = _tune(ch, 0.5)
         st0 = ch.stats()
         w_s, k_s = _timed(ch, ch.sweep, sweeps, seed)

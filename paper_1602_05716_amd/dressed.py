@@ -38,7 +38,6 @@ def _log(*a):
 
 def run(n: int, sweeps: int, equil: int, every: int, rmax: float, bins: int, seed: int, chunk: int = 100,
         margin: float | None = None, debye_A: float = inputs.PAPER_DEBYE_A):
-    import torch
     from . import mc
     t0 = time.perf_counter()
     sy = inputs.three_to_one(n, seed, debye_A)
@@ -46,10 +45,9 @@ def run(n: int, sweeps: int, equil: int, every: int, rmax: float, bins: int, see
     md = sy.R / 3.0  # cube side 2 md = L / 3
     if margin is None:  # every neighbour counted at least ten bare Debye lengths inside the wall
         margin = 10.0 * sy.meta["kappa_inv"]
-    stream = torch.cuda.Stream()
+    # the handle's own stream: nothing here needs another GPU runtime
     with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision="fp32", max_disp=md, resum_every=100,
-                  rdf_every=every, rdf_bins=bins, rdf_rmax=rmax, rdf_margin=margin,
-                  hip_stream=stream.cuda_stream) as ch:
+                  rdf_every=every, rdf_bins=bins, rdf_rmax=rmax, rdf_margin=margin) as ch:
         done = 0
         while done < equil:
             k = min(chunk, equil - done)
