@@ -194,7 +194,7 @@ int mc_rdf(mc_handle* h, int32_t bins, double* g, uint64_t* counts, uint64_t* ce
  * network again with mc_set_surrogate), and the autotuned schedule (planned
  * again from the defaults).  mc_load creates a handle from such a file; opt
  * NULL means the saved options (without their stream), otherwise opt is used
- * and must have the saved precision and rdf_bins.  The random stream is a
+ * and must have the saved precision, rdf_bins, rdf_rmax and rdf_margin.  The random stream is a
  * function of (seed, sweep, ion, chain), so sweeps run after mc_load with the
  * same seed reproduce the ones an uninterrupted chain would run, bit for bit.
  * The file is in host byte order for this library version.  Errors: MC_E_ARG

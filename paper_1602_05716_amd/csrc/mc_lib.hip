@@ -1525,8 +1525,11 @@ int mc_load(const char* path, const mc_options* opt_in, mc_handle** out) {
     mc_options opt = saved;
     if (opt_in) {
         opt = *opt_in;
-        if (opt.precision != saved.precision || opt.rdf_bins != saved.rdf_bins)
-            return fail(nullptr, MC_E_ARG, "precision and rdf_bins must be those of the checkpoint");
+        // the restored g(r) counts belong to the saved histogram and centre rule
+        if (opt.precision != saved.precision || opt.rdf_bins != saved.rdf_bins ||
+            opt.rdf_rmax != saved.rdf_rmax || opt.rdf_margin != saved.rdf_margin)
+            return fail(nullptr, MC_E_ARG,
+                        "precision, rdf_bins, rdf_rmax and rdf_margin must be those of the checkpoint");
     }
     int rc = check_options(opt);
     if (rc) return rc;

@@ -85,6 +85,8 @@ def test_batch_resume_and_options(tmp_path):
             assert abs(c.energy(k) - ea[k]) <= 1e-9 * max(1.0, abs(ea[k]))
     with pytest.raises(mc.MCError):
         mc.Batch.load(path, precision="fp64")
+    with pytest.raises(mc.MCError):  # another g(r) histogram than the saved counts'
+        mc.Batch.load(path, precision="fp32", rdf_rmax=5.0)
 
 
 def test_production_driver_runs_and_pools(tmp_path):
