@@ -47,6 +47,28 @@ def test_philox_matches_torch_engine(oracle):
         assert got.tolist() == expect.tolist(), r
 
 
+def test_philox_matches_rocrand_rounds(oracle):
+    """The same blocks against a second independent implementation: the ten
+    rounds of rocRAND's header-only Philox4x32-10 engine, built for the host
+    with hipcc.  Unlike a stream interface it takes any 128-bit counter."""
+    hipcc = "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not installed")
+    src = os.path.join(ROOT, "tests", "helpers", "philox_rocrand_ref.cpp")
+    exe = os.path.join("/tmp", "philox_rocrand_ref_%d" % os.getpid())
+    subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O1", "-std=c++17", "-o", exe, src])
+    rng = np.random.default_rng(8)
+    rows = [[0, 0, 0, 0, 0, 0], [0xFFFFFFFF] * 6, [0, 0, 0, 0xFFFFFFFF, 1, 0]]
+    rows += rng.integers(0, 2**32, size=(500, 6), dtype=np.uint64).tolist()
+    text = "\n".join(" ".join(str(int(v)) for v in r) for r in rows) + "\n"
+    out = subprocess.run([exe], input=text, capture_output=True, text=True, check=True).stdout
+    os.unlink(exe)
+    ref = np.array([[int(t) for t in line.split()] for line in out.strip().splitlines()], np.uint64)
+    assert ref.shape == (len(rows), 4)
+    for r, expect in zip(rows, ref):
+        assert oracle.philox(r[:4], r[4:]).tolist() == expect.tolist(), r
+
+
 def test_move_words_counter_layout(oracle):
     """Move (ion i, sweep s, chain c) uses counter (i, s, c, tag), key = seed words."""
     seed = 0x0123456789ABCDEF
