@@ -151,3 +151,26 @@ def test_reduction_rejects_batches():
     systems = [_sys(50, 50, seed=30 + k) for k in range(2)]
     with mc.Batch(systems) as b:
         assert mc.lib().mc_sweep_reduction(b.h, 1, 1) == -1  # MC_E_ARG
+
+
+def test_reduction_interleaves_resum_and_rdf_like_the_sweep_kernel():
+    """Re-sum and g(r) intervals inside mc_sweep_reduction: the same positions,
+    re-sum count, g(r) counts and (to rounding) energies as mc_sweep."""
+    from paper_1602_05716_amd import mc
+    sy = _sys(200, 400, q=(2.0, -1.0), s=(1.0, 0.8), phi=0.08, seed=17)
+    kw = dict(precision="fp64", max_disp=0.6, resum_every=3, rdf_every=2, rdf_bins=50, rdf_rmax=5.0)
+    out = []
+    for scheme in ("sweep", "reduce"):
+        _say("reduction intervals scheme=%s" % scheme)
+        with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, **kw) as ch:
+            (ch.sweep_reduction if scheme == "reduce" else ch.sweep)(7, 5)
+            st = ch.stats()
+            out.append(dict(x=ch.positions(), e=ch.energy(exact=True), es=ch.energy_series(7), rdf=ch.rdf(),
+                            resums=st["resums"], moves=st["moves"], acc=st["accepted"]))
+    a, b = out
+    assert np.array_equal(a["x"], b["x"])
+    assert a["resums"] == b["resums"] == 2 and a["moves"] == b["moves"] == 7 * sy.n and a["acc"] == b["acc"]
+    assert np.allclose(a["es"], b["es"], rtol=1e-10, atol=1e-10)
+    assert abs(a["e"][0] - b["e"][0]) <= 1e-9 * max(1.0, abs(a["e"][1])) and a["e"][1] == b["e"][1]
+    assert a["rdf"]["samples"] == b["rdf"]["samples"] == 3
+    assert np.array_equal(a["rdf"]["counts"], b["rdf"]["counts"])
