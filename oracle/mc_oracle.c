@@ -43,6 +43,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10, as defined by Salmon, Moraes, Dror and Shaw, "Parallel      */
@@ -95,6 +98,16 @@ void orc_move_words(uint64_t seed, uint32_t chain, uint32_t sweep, uint32_t i,
 /* ------------------------------------------------------------------------ */
 
 /* Squared distance, summed left to right with no fused multiply-add. */
+/* Threads the partner sum may use: 1, or the OpenMP build's thread count. */
+int32_t orc_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 static double dist2(const double* a, const double* b)
 {
     double dx = a[0] - b[0];
@@ -131,6 +144,9 @@ double orc_delta_energy(int32_t n, const double* xyz, const double* q,
     const double* xi = xyz + 3 * i;
     double s = 0.0;
     int ov = 0;
+    /* the OpenMP build (timing only; it sums in another order) splits the
+       partners over the host's threads; the oracle proper ignores this */
+#pragma omp parallel for schedule(static) reduction(+ : s) reduction(| : ov) if (n >= 4096)
     for (int32_t j = 0; j < n; ++j) {
         if (j == i) continue;
         const double* xj = xyz + 3 * j;
@@ -155,6 +171,26 @@ static int outside_wall(const double* x, double R, double sigma)
 int32_t orc_outside_wall(const double* x, double R, double sigma)
 {
     return outside_wall(x, R, sigma);
+}
+
+/*
+ * Contact margin of a trial position: min over j != i of r~_ij / sigma_ij - 1
+ * (negative when the trial overlaps an ion).  Not part of the chain: the
+ * parity tests use it to tell a decision taken at contact, within float
+ * rounding of sigma_ij, from a wrong one.
+ */
+static double contact_margin(int32_t n, const double* xyz, const double* sigma, int32_t i,
+                             const double* xt)
+{
+    double m = INFINITY;
+    for (int32_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double contact = 0.5 * (sigma[i] + sigma[j]);
+        if (!(contact > 0.0)) continue;
+        double g = sqrt(dist2(xt, xyz + 3 * j)) / contact - 1.0;
+        if (g < m) m = g;
+    }
+    return m;
 }
 
 /* Metropolis test, Eq. (trial-outcome) with Algorithm 4's uniform. */
@@ -240,7 +276,7 @@ int64_t orc_replay_f32(int32_t n, float* xyz, const double* q, const double* sig
                        double R, double lB, float D, uint64_t seed, uint32_t chain,
                        uint32_t sweep0, int64_t n_moves, const uint8_t* acc_given,
                        const uint8_t* eval_mask, double* de_out, double* u3_out,
-                       uint8_t* flags_out, uint8_t* own_out)
+                       uint8_t* flags_out, uint8_t* own_out, double* margin_out)
 {
     double* xd = (double*)malloc(sizeof(double) * 3 * (size_t)n);
     if (!xd) return -1;
@@ -268,6 +304,7 @@ int64_t orc_replay_f32(int32_t n, float* xyz, const double* q, const double* sig
         if (evaluate) {
             dE = orc_delta_energy(n, xd, q, sigma, i, xt, lB, &ov);
             own = !wall && !ov && metropolis(dE, u3);
+            if (margin_out) margin_out[m] = contact_margin(n, xd, sigma, i, xt);
         }
         int acc = acc_given ? (int)acc_given[m] : own;
         if (evaluate && acc != own) ++mismatches;
@@ -430,7 +467,10 @@ static int within(const double* a, const double* b, double rc)
  * rejection, bit4 stage-2 rejection -- of the oracle's own evaluation),
  * own decision, features [256] (phi(x_i), phi(x~_i); conflict moves too),
  * u3 and u2.  eval_mask (nullable) limits the evaluation to marked moves
- * (replays only).  *e_run accumulates accepted dE.  Returns the number of
+ * (replays only).  *e_run accumulates accepted dE.  snap_out (nullable)
+ * receives the positions after every completed sweep of the run,
+ * [n_moves / n][n][3]; margin_out (nullable) the contact margin of every
+ * evaluated trial.  Returns the number of
  * evaluated moves whose given decision differs from the oracle's, or -1 if
  * a DA run with band > 0 does not start at sweep 0 (the pending trials of
  * the previous sweep are not known; with DA off the conflict flags of the
@@ -442,7 +482,8 @@ int64_t orc_da_run(int32_t n, double* xyz, const double* q, const double* sigma,
                    double rc, int32_t band, int32_t da_on, const uint8_t* acc_given,
                    const uint8_t* eval_mask, int64_t out_cap, double* de_out,
                    double* deh_out, uint8_t* flags_out, uint8_t* own_out,
-                   int32_t* feat_out, double* u3_out, double* u2_out, double* e_run)
+                   int32_t* feat_out, double* u3_out, double* u2_out, double* e_run,
+                   double* snap_out, double* margin_out)
 {
     if (band > 0 && sweep0 != 0 && da_on) return -1;
     const int32_t group = 64;
@@ -488,6 +529,7 @@ int64_t orc_da_run(int32_t n, double* xyz, const double* q, const double* sigma,
             int wall = outside_wall(xt, R, sigma[i]);
             int ov = 0;
             dE = orc_delta_energy(n, xyz, q, sigma, i, xt, lB, &ov);
+            if (margin_out && m < out_cap) margin_out[m] = contact_margin(n, xyz, sigma, i, xt);
             /* conflict: pending ions near x_i or x~_i in either of their positions */
             int conflict = 0;
             int64_t g = (int64_t)sweep * nb + i / group;
@@ -536,6 +578,8 @@ int64_t orc_da_run(int32_t n, double* xyz, const double* q, const double* sigma,
             if (e_run) *e_run += dE;
             for (int k = 0; k < 3; ++k) xyz[3 * i + k] = xt[k];
         }
+        if (snap_out && i == n - 1)
+            memcpy(snap_out + (size_t)(m / n) * 3 * (size_t)n, xyz, sizeof(double) * 3 * (size_t)n);
     }
     free(old);
     free(tri);

@@ -9,8 +9,9 @@ Markov chain itself; this module adds
   * g_ab(r) normalisation of the integer pair counts (Sec. 5.2, pair
     correlation functions),
   * the integrated autocorrelation time T_c = 1/2 + sum_k C_k of the energy
-    series (Sec. 5.2, definitions of C_n and T_c), truncated with Sokal's
-    automatic window (the paper does not say where to stop the sum),
+    series (Sec. 5.2, definitions of C_n and T_c), the sum stopped at the
+    first non-positive sum of a pair of lags (the paper does not say where
+    to stop it),
   * Debye-Hueckel closed forms (Sec. 5.1, Eq. (alpha-kappa_0) and the PB pair
     potential) used by the dilute-limit test.
 """
@@ -34,70 +35,91 @@ _f64p = ctypes.POINTER(ctypes.c_double)
 _f32p = ctypes.POINTER(ctypes.c_float)
 
 
+_LIB_OMP = os.path.join(_HERE, "libmc_oracle_omp.so")
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, no fused multiply-add)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
-                               "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (-O2, no fused multiply-add), and its
+    OpenMP build, which only the CPU timing uses."""
+    for lib_path, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib_path) or os.path.getmtime(lib_path) < os.path.getmtime(_SRC):
+            tmp = lib_path + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                                   "-std=c99", "-fPIC", "-shared"] + extra + ["-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, lib_path)
     return _LIB
 
 
 _lib = None
+_lib_omp = None
+
+
+def lib_omp():
+    """The OpenMP build (CPU timing only)."""
+    global _lib_omp
+    if _lib_omp is None:
+        build()
+        _lib_omp = _declare(ctypes.CDLL(_LIB_OMP))
+    return _lib_omp
 
 
 def lib():
     global _lib
     if _lib is None:
         build()
-        L = ctypes.CDLL(_LIB)
-        L.orc_philox.argtypes = [_u32p, _u32p, _u32p]
-        L.orc_philox.restype = None
-        L.orc_move_words.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
-                                     ctypes.c_uint32, ctypes.c_uint32, _u32p]
-        L.orc_move_words.restype = None
-        L.orc_total_energy.argtypes = [ctypes.c_int32, _f64p, _f64p, ctypes.c_double]
-        L.orc_total_energy.restype = ctypes.c_double
-        L.orc_delta_energy.argtypes = [ctypes.c_int32, _f64p, _f64p, _f64p, ctypes.c_int32,
-                                       _f64p, ctypes.c_double, _i32p]
-        L.orc_delta_energy.restype = ctypes.c_double
-        L.orc_outside_wall.argtypes = [_f64p, ctypes.c_double, ctypes.c_double]
-        L.orc_outside_wall.restype = ctypes.c_int32
-        L.orc_trial_f64.argtypes = [_f64p, _u32p, ctypes.c_double, _f64p]
-        L.orc_trial_f64.restype = None
-        L.orc_sweeps_f64.argtypes = [ctypes.c_int32, _f64p, _f64p, _f64p, ctypes.c_double,
-                                     ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
-                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int32, _f64p,
-                                     _u8p, _f64p, _u8p, ctypes.c_int64, _f64p]
-        L.orc_sweeps_f64.restype = ctypes.c_int64
-        L.orc_replay_f32.argtypes = [ctypes.c_int32, _f32p, _f64p, _f64p, ctypes.c_double,
-                                     ctypes.c_double, ctypes.c_float, ctypes.c_uint64,
-                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64, _u8p,
-                                     _u8p, _f64p, _f64p, _u8p, _u8p]
-        L.orc_replay_f32.restype = ctypes.c_int64
-        L.orc_rdf_counts.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int32,
-                                     ctypes.c_double, ctypes.c_double, ctypes.c_int32, _u64p,
-                                     _u64p]
-        L.orc_rdf_counts.restype = None
-        L.orc_da_nparam.argtypes = []
-        L.orc_da_nparam.restype = ctypes.c_int32
-        L.orc_bf16_round.argtypes = [ctypes.c_double]
-        L.orc_bf16_round.restype = ctypes.c_double
-        L.orc_da_features.argtypes = [ctypes.c_int32, _f64p, _f64p, ctypes.c_int32, _f64p,
-                                      ctypes.c_double, _i32p]
-        L.orc_da_features.restype = None
-        L.orc_mlp_eps.argtypes = [_f64p, _i32p]
-        L.orc_mlp_eps.restype = ctypes.c_double
-        L.orc_da_run.argtypes = [ctypes.c_int32, _f64p, _f64p, _f64p, ctypes.c_double,
-                                 ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
-                                 ctypes.c_uint32, ctypes.c_int64, ctypes.c_int32, _f64p,
-                                 ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _u8p, _u8p,
-                                 ctypes.c_int64, _f64p, _f64p, _u8p, _u8p, _i32p, _f64p, _f64p,
-                                 _f64p]
-        L.orc_da_run.restype = ctypes.c_int64
-        _lib = L
+        _lib = _declare(ctypes.CDLL(_LIB))
     return _lib
+
+
+def _declare(L):
+    """Argument and result types of the oracle's exported functions."""
+    L.orc_philox.argtypes = [_u32p, _u32p, _u32p]
+    L.orc_philox.restype = None
+    L.orc_move_words.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                 ctypes.c_uint32, ctypes.c_uint32, _u32p]
+    L.orc_move_words.restype = None
+    L.orc_total_energy.argtypes = [ctypes.c_int32, _f64p, _f64p, ctypes.c_double]
+    L.orc_total_energy.restype = ctypes.c_double
+    L.orc_delta_energy.argtypes = [ctypes.c_int32, _f64p, _f64p, _f64p, ctypes.c_int32,
+                                   _f64p, ctypes.c_double, _i32p]
+    L.orc_delta_energy.restype = ctypes.c_double
+    L.orc_outside_wall.argtypes = [_f64p, ctypes.c_double, ctypes.c_double]
+    L.orc_outside_wall.restype = ctypes.c_int32
+    L.orc_trial_f64.argtypes = [_f64p, _u32p, ctypes.c_double, _f64p]
+    L.orc_trial_f64.restype = None
+    L.orc_sweeps_f64.argtypes = [ctypes.c_int32, _f64p, _f64p, _f64p, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                 ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int32, _f64p,
+                                 _u8p, _f64p, _u8p, ctypes.c_int64, _f64p]
+    L.orc_sweeps_f64.restype = ctypes.c_int64
+    L.orc_replay_f32.argtypes = [ctypes.c_int32, _f32p, _f64p, _f64p, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_float, ctypes.c_uint64,
+                                 ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64, _u8p,
+                                 _u8p, _f64p, _f64p, _u8p, _u8p, _f64p]
+    L.orc_replay_f32.restype = ctypes.c_int64
+    L.orc_rdf_counts.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int32,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_int32, _u64p,
+                                 _u64p]
+    L.orc_rdf_counts.restype = None
+    L.orc_da_nparam.argtypes = []
+    L.orc_da_nparam.restype = ctypes.c_int32
+    L.orc_bf16_round.argtypes = [ctypes.c_double]
+    L.orc_bf16_round.restype = ctypes.c_double
+    L.orc_da_features.argtypes = [ctypes.c_int32, _f64p, _f64p, ctypes.c_int32, _f64p,
+                                  ctypes.c_double, _i32p]
+    L.orc_da_features.restype = None
+    L.orc_mlp_eps.argtypes = [_f64p, _i32p]
+    L.orc_mlp_eps.restype = ctypes.c_double
+    L.orc_da_run.argtypes = [ctypes.c_int32, _f64p, _f64p, _f64p, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                             ctypes.c_uint32, ctypes.c_int64, ctypes.c_int32, _f64p,
+                             ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _u8p, _u8p,
+                             ctypes.c_int64, _f64p, _f64p, _u8p, _u8p, _i32p, _f64p, _f64p,
+                             _f64p, _f64p, _f64p]
+    L.orc_da_run.restype = ctypes.c_int64
+    L.orc_threads.argtypes = []
+    L.orc_threads.restype = ctypes.c_int32
+    return L
 
 
 def _p(a, t):
@@ -153,7 +175,11 @@ class Chain:
     ``run(n)`` performs n sweeps; each sweep tries ions 0..N-1 once, in order.
     """
 
-    def __init__(self, xyz, q, sigma, R, lB, D, seed, chain=0, sweep=0):
+    def __init__(self, xyz, q, sigma, R, lB, D, seed, chain=0, sweep=0, threaded=False):
+        # threaded: run on the OpenMP build (all host threads, another
+        # summation order); for timing the CPU baseline only
+        self._L = lib_omp() if threaded else lib()
+        self.threads = int(self._L.orc_threads())
         self.x = np.array(xyz, np.float64).reshape(-1, 3).copy()
         self.q = np.ascontiguousarray(q, np.float64)
         self.sigma = np.ascontiguousarray(sigma, np.float64)
@@ -170,7 +196,7 @@ class Chain:
         fl = np.zeros(max(cap, 1), np.uint8)
         es = np.zeros(max(n_sweeps, 1), np.float64) if series else None
         e = ctypes.c_double(self.e_run)
-        nacc = lib().orc_sweeps_f64(self.n, _p(self.x, _f64p), _p(self.q, _f64p),
+        nacc = self._L.orc_sweeps_f64(self.n, _p(self.x, _f64p), _p(self.q, _f64p),
                                     _p(self.sigma, _f64p), self.R, self.lB, self.D,
                                     self.seed, self.chain, self.sweep, int(n_sweeps),
                                     ctypes.byref(e), _p(acc, _u8p), _p(de, _f64p),
@@ -191,9 +217,11 @@ def replay_f32(xyz_f32, q, sigma, R, lB, D, seed, chain, sweep0, n_moves, acc_gi
     """Exact double dE of each move along a float-state trajectory.
 
     The trajectory follows ``acc_given`` (e.g. another implementation's
-    decisions); with ``eval_mask`` only the marked moves are evaluated.  Returns dict with dE, u3, flags (bit0 wall, bit1 overlap),
-    the oracle's own decision per move, the final float state and the number
-    of moves whose given decision differs from the oracle's.
+    decisions); with ``eval_mask`` only the marked moves are evaluated.
+    Returns a dict with dE, u3, flags (bit0 wall, bit1 overlap), the contact
+    margin min_j r~_ij / sigma_ij - 1 of each evaluated trial, the oracle's
+    own decision per move, the final float state and the number of moves
+    whose given decision differs from the oracle's.
     """
     x = np.array(xyz_f32, np.float32).reshape(-1, 3).copy()
     qq = np.ascontiguousarray(q, np.float64)
@@ -203,13 +231,15 @@ def replay_f32(xyz_f32, q, sigma, R, lB, D, seed, chain, sweep0, n_moves, acc_gi
     u3 = np.zeros(n_moves, np.float64)
     fl = np.zeros(n_moves, np.uint8)
     own = np.zeros(n_moves, np.uint8)
+    margin = np.full(n_moves, np.inf)
     ag = None if acc_given is None else np.ascontiguousarray(acc_given, np.uint8)
     em = None if eval_mask is None else np.ascontiguousarray(eval_mask, np.uint8)
     mism = lib().orc_replay_f32(n, _p(x, _f32p), _p(qq, _f64p), _p(ss, _f64p), R, lB,
                                 np.float32(D), seed, chain, sweep0, int(n_moves),
                                 _p(ag, _u8p), _p(em, _u8p), _p(de, _f64p), _p(u3, _f64p),
-                                _p(fl, _u8p), _p(own, _u8p))
-    return {"dE": de, "u3": u3, "flags": fl, "own": own, "xyz": x, "mismatches": int(mism)}
+                                _p(fl, _u8p), _p(own, _u8p), _p(margin, _f64p))
+    return {"dE": de, "u3": u3, "flags": fl, "own": own, "xyz": x, "mismatches": int(mism),
+            "margin": margin}
 
 
 # --------------------------------------------------------------------------- #
@@ -268,20 +298,38 @@ def autocorr(series, max_lag=None):
     return c / var
 
 
-def tau_int(series, c_window=5.0):
-    """T_c = 1/2 + sum_{k>=1} C_k, the sum stopped at the first M >= c T_c(M)."""
-    c = autocorr(series)
-    tau = 0.5
-    for m in range(1, len(c)):
-        tau += c[m]
-        if m >= c_window * tau:
-            return tau
+def tau_int(series):
+    """T_c = 1/2 + sum_{k>=1} C_k (Sec. 5.2).
+
+    The paper does not say where the infinite sum stops.  Written as
+    T_c = -1/2 + sum_{m>=0} (C_{2m} + C_{2m+1}), the sum runs over the pairs
+    of lags up to, not including, the first pair whose sum is not positive
+    (Geyer's initial positive sequence, Stat. Sci. 7, 1992).  Unlike a window
+    in units of T_c it also converges for negatively correlated series.
+    NaN for a constant series (C_n undefined).
+    """
+    e = np.asarray(series, np.float64)
+    n = len(e)
+    d = e - e.mean()
+    var = np.dot(d, d) / n
+    if n < 2 or var == 0.0:
+        return float("nan")
+
+    def c(k):  # C_k, the normalised autocovariance at lag k
+        return np.dot(d[: n - k], d[k:]) / n / var
+
+    tau = -0.5
+    for m in range(n // 2):
+        pair = c(2 * m) + c(2 * m + 1)
+        if not pair > 0.0:
+            break
+        tau += pair
     return tau
 
 
-def ess(series, c_window=5.0):
+def ess(series):
     """Effective sample size n / (2 T_c)."""
-    return len(series) / (2.0 * tau_int(series, c_window))
+    return len(series) / (2.0 * tau_int(series))
 
 
 # --------------------------------------------------------------------------- #
@@ -355,10 +403,12 @@ def mlp_eps(params, feat) -> float:
 
 
 def da_run(xyz, q, sigma, R, lB, D, seed, chain, sweep0, n_moves, params, rc=4.0, band=0, da_on=1,
-           f32=False, acc_given=None, eval_mask=None, features=False):
+           f32=False, acc_given=None, eval_mask=None, features=False, snapshots=False):
     """DA chain (own decisions) or replay (``acc_given``); returns a dict with
     the final state ``x`` and per-move dE, dEh, flags, own, u3, u2 (and
-    features [n_moves, 256] if asked)."""
+    features [n_moves, 256], and the positions after every completed sweep
+    [sweeps, n, 3] as ``snapshots``, if asked) and the contact margin
+    min_j r~_ij / sigma_ij - 1 of each evaluated trial."""
     x = np.array(xyz, np.float64).reshape(-1, 3).copy()
     if f32:
         x = x.astype(np.float32).astype(np.float64)
@@ -371,15 +421,19 @@ def da_run(xyz, q, sigma, R, lB, D, seed, chain, sweep0, n_moves, params, rc=4.0
     feat = np.zeros((m, 2 * DA_IN), np.int32) if features else None
     ag = None if acc_given is None else np.ascontiguousarray(acc_given, np.uint8)
     em = None if eval_mask is None else np.ascontiguousarray(eval_mask, np.uint8)
+    snap = np.zeros((m // len(qq), len(qq), 3)) if snapshots else None
+    margin = np.full(m, np.inf)
     e = ctypes.c_double(0.0)
     mism = lib().orc_da_run(len(qq), _p(x, _f64p), _p(qq, _f64p), _p(ss, _f64p), R, lB, D, seed, chain,
                             sweep0, m, 1 if f32 else 0, _p(pp, _f64p), rc, band, da_on, _p(ag, _u8p),
                             _p(em, _u8p), m, _p(de, _f64p), _p(deh, _f64p), _p(fl, _u8p), _p(own, _u8p),
-                            _p(feat, _i32p), _p(u3, _f64p), _p(u2, _f64p), ctypes.byref(e))
+                            _p(feat, _i32p), _p(u3, _f64p), _p(u2, _f64p), ctypes.byref(e),
+                            _p(snap, _f64p), _p(margin, _f64p))
     if mism < 0:
         raise ValueError("orc_da_run failed (%d)" % mism)
     return {"x": x, "dE": de, "dEh": deh, "flags": fl, "own": own, "u3": u3, "u2": u2,
-            "features": feat, "mismatches": int(mism), "e_change": e.value}
+            "features": feat, "mismatches": int(mism), "e_change": e.value, "snapshots": snap,
+            "margin": margin}
 
 
 def mlp_forward(params, X, rounding=True):

@@ -4,9 +4,10 @@ sample size.
 Paper: Liang, Xing, Li, arXiv:1602.05716, Sec. 5.2 -- autocorrelation function
 C_n of the total energy and the integrated autocorrelation time
 T_c = 1/2 + sum_{k>=1} C_k.  The paper does not say where the infinite sum is
-cut; here it stops at the first window M >= c T_c(M) (Sokal's automatic
-window, c = 5).  The effective sample size of n correlated values is
-n / (2 T_c).
+cut; here it runs over pairs of lags, C_{2m} + C_{2m+1}, up to the first pair
+whose sum is not positive (Geyer's initial positive sequence, 1992), which
+also converges for negatively correlated series.  The effective sample size
+of n correlated values is n / (2 T_c).
 """
 from __future__ import annotations
 
@@ -26,18 +27,24 @@ def autocorrelation(series: np.ndarray, max_lag: int | None = None) -> np.ndarra
     return acov / acov[0] if acov[0] > 0 else np.zeros(max_lag + 1)
 
 
-def integrated_time(series: np.ndarray, window_c: float = 5.0) -> float:
-    c = autocorrelation(series)
-    tau = 0.5
-    for m in range(1, len(c)):
-        tau += c[m]
-        if m >= window_c * tau:
-            break
-    return max(tau, 0.5)
+def integrated_time(series: np.ndarray) -> float:
+    """T_c = 1/2 + sum_{k>=1} C_k = -1/2 + sum_{m>=0} (C_{2m} + C_{2m+1}),
+    summed over pairs of lags up to the first pair whose sum is not positive.
+    NaN for a constant series or fewer than two values."""
+    x = np.asarray(series, np.float64)
+    if len(x) < 2 or not np.any(x != x[0]):
+        return float("nan")
+    c = autocorrelation(x)
+    npairs = len(c) // 2
+    pairs = c[0:2 * npairs:2] + c[1:2 * npairs:2]
+    stop = np.flatnonzero(~(pairs > 0.0))
+    m = int(stop[0]) if stop.size else npairs
+    return float(-0.5 + np.sum(pairs[:m]))
 
 
-def effective_samples(series: np.ndarray, window_c: float = 5.0) -> float:
-    return len(series) / (2.0 * integrated_time(series, window_c))
+def effective_samples(series: np.ndarray) -> float:
+    """n / (2 T_c)."""
+    return len(series) / (2.0 * integrated_time(series))
 
 
 # --------------------------------------------------------------------------- #

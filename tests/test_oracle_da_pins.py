@@ -216,3 +216,48 @@ def test_backprop_matches_central_differences(oracle):
               oracle.mlp_loss_grad(pm, Xo, Xn, y, rounding=False)[0]) / (2 * h)
         assert fd == pytest.approx(g[k], rel=1e-5, abs=1e-8), k
     assert loss > 0
+
+
+@pytest.mark.parametrize("band,n,R", [(1, 192, 8.0), (2, 192, 8.0), (3, 256, 8.8)])
+def test_conflict_rule_keeps_independent_ions_uniform(oracle, band, n, R):
+    """Exactness of the conflict rule at band >= 1, independent of how the
+    rule is tiled: point ions (sigma 1e-3) with l_B = 1e-6 are, to 1e-5 in
+    the Boltzmann factor, independent and uniform in the ball, so g_ab = 1 at
+    every r (the closed form pinned for the estimator above).  The network's
+    output layer is scaled by 1/l_B so that stage 1 rejects freely
+    (dEh of order 1 kT); a conflict rule that depends on which of the two
+    positions {x_i, x~_i} is the current one leaves the chain with a
+    different stationary law (measured: g about 0.5 below rc)."""
+    rng = np.random.default_rng(5)
+    lB, rc, sig = 1e-6, 1.0, 1e-3
+    p = _params(rng, 0.3)
+    w3 = len(p) - 129
+    p[w3:w3 + 128] = oracle.bf16(p[w3:w3 + 128] / lB)
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    types = (np.arange(n) % 2).astype(np.int32)
+    v = rng.normal(size=(n, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    x = v * ((R - 0.5 * sig) * rng.uniform(size=n) ** (1.0 / 3.0))[:, None]
+    sweeps = 400
+    r = oracle.da_run(x, q, np.full(n, sig), R, lB, 2.0, 8, 0, 0, n * sweeps, p, rc=rc, band=band,
+                      snapshots=True)
+    fl = r["flags"]
+    conflict = ((fl >> 2) & 1).mean()
+    stage1_rej = ((fl >> 3) & 1).mean()
+    assert 0.15 < conflict < 0.85 and stage1_rej * len(fl) > 500, (conflict, stage1_rej)
+    bins = 4
+    C = np.zeros((2, 2, bins), np.uint64)
+    ce = np.zeros(2, np.uint64)
+    for s in r["snapshots"][10:]:
+        c, cc = oracle.rdf_counts(s, types, 2, R, rc, bins)
+        C += c
+        ce += cc
+    # pooled over the shells r >= rc / 4 (bin 0 holds few pairs)
+    Cp = C[:, :, 1:].sum(axis=2).astype(float)
+    dr = rc / bins
+    vol = 4.0 / 3.0 * np.pi * ((bins * dr) ** 3 - dr ** 3)
+    for a in range(2):
+        for b in range(2):
+            nb = (n // 2 - (1 if a == b else 0)) / (4.0 / 3.0 * np.pi * (R - 0.5 * sig) ** 3)
+            g = Cp[a, b] / (float(ce[a]) * nb * vol)
+            assert abs(g - 1.0) < 0.12, (band, a, b, g, Cp[a, b])

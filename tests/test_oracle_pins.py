@@ -423,15 +423,84 @@ def test_rdf_pair_symmetry_when_every_ion_is_a_centre(oracle):
 # Autocorrelation time                                                        #
 # --------------------------------------------------------------------------- #
 
-def test_tau_int_on_ar1(oracle):
+def _ar1(rho, n, seed):
+    from scipy.signal import lfilter
+    return lfilter([1.0], [1.0, -rho], np.random.default_rng(seed).normal(size=n))
+
+
+@pytest.mark.parametrize("rho", [-0.6, -0.3, 0.0, 0.5, 0.8])
+def test_tau_int_on_ar1(oracle, rho):
     """AR(1) with coefficient rho has C_k = rho^k, so T_c = (1 + rho) / (2 (1 - rho))
-    under T_c = 1/2 + sum_k C_k (Sec. 5.2)."""
-    rng = np.random.default_rng(12)
-    for rho in (0.0, 0.5, 0.8):
-        n = 200_000
-        eps = rng.normal(size=n)
-        x = np.zeros(n)
-        for t in range(1, n):
-            x[t] = rho * x[t - 1] + eps[t]
-        expect = (1 + rho) / (2 * (1 - rho))
-        assert oracle.tau_int(x) == pytest.approx(expect, rel=0.08, abs=0.02)
+    under T_c = 1/2 + sum_k C_k (Sec. 5.2), for negative rho as well."""
+    x = _ar1(rho, 200_000, 12)
+    expect = (1 + rho) / (2 * (1 - rho))
+    assert oracle.tau_int(x) == pytest.approx(expect, rel=0.06, abs=0.01)
+    assert oracle.ess(x) == pytest.approx(len(x) / (2 * oracle.tau_int(x)), rel=1e-15)
+
+
+def test_tau_int_of_a_moving_average(oracle):
+    """x_t = e_t + e_{t-1} has C_1 = 1/2 and C_k = 0 beyond, so T_c = 1
+    exactly; the estimate must not pick up the noise of the empty lags."""
+    e = np.random.default_rng(13).normal(size=400_001)
+    x = e[1:] + e[:-1]
+    assert oracle.tau_int(x) == pytest.approx(1.0, abs=0.02)
+    assert math.isnan(oracle.tau_int(np.full(50, 3.0)))
+
+
+# --------------------------------------------------------------------------- #
+# g(r) normalisation                                                          #
+# --------------------------------------------------------------------------- #
+
+def _uniform_ball_counts(n_of_type, a_of_type, R, rmax, bins, samples, seed):
+    """Counts of the Sec. 5.2 estimator (centres |x| <= R - rmax, ordered
+    pairs) over i.i.d. configurations: every ion of type b uniform in the
+    ball of radius a_b, independently of all others (no hard core)."""
+    rng = np.random.default_rng(seed)
+    types = np.concatenate([np.full(nb, b) for b, nb in enumerate(n_of_type)])
+    nt, n = len(n_of_type), len(types)
+    radii = np.array([a_of_type[t] for t in types])
+    counts = np.zeros((nt, nt, bins), np.int64)
+    centres = np.zeros(nt, np.int64)
+    chunk = 4000
+    for s0 in range(0, samples, chunk):
+        m = min(chunk, samples - s0)
+        v = rng.normal(size=(m, n, 3))
+        v /= np.sqrt(np.einsum("mnk,mnk->mn", v, v))[..., None]
+        x = v * (radii * rng.uniform(size=(m, n)) ** (1.0 / 3.0))[..., None]
+        cen = np.einsum("mnk,mnk->mn", x, x) <= (R - rmax) ** 2
+        d = np.zeros((m, n, n))
+        for c in range(3):
+            d += (x[:, :, None, c] - x[:, None, :, c]) ** 2
+        d = np.sqrt(d)
+        k = np.floor(d / (rmax / bins)).astype(np.int64)
+        ok = cen[:, :, None] & (d < rmax) & ~np.eye(n, dtype=bool)[None]
+        pair_type = (types[:, None] * nt + types[None, :]) * bins
+        idx = (pair_type[None] + np.minimum(k, bins - 1))[ok]
+        counts += np.bincount(idx, minlength=nt * nt * bins).reshape(nt, nt, bins)
+        centres += np.bincount(np.broadcast_to(types, cen.shape)[cen], minlength=nt)
+    return counts, centres
+
+
+def test_rdf_normalise_is_one_for_independent_ions(oracle):
+    """Ions placed independently and uniformly, type b in the ball of radius
+    R - sigma_b / 2: a neighbour of type b lies in shell k of a centre with
+    probability V_k / ((4/3) pi (R - sigma_b/2)^3) for each of the N_b -
+    delta_ab other ions, so the pooled estimator g_ab(r_k) has expectation
+    1 in every shell that lies inside the neighbours' ball for every centre
+    (r_{k+1} <= rmax - sigma_b / 2).  Closed form, no Markov chain; a density
+    without the ion radius or a neighbour count that includes the centre is
+    off by 5-30 %."""
+    n_of_type, sig = [12, 16], [1.0, 0.4]
+    R, rmax, bins, samples = 6.0, 2.5, 5, 60_000
+    a_of_type = [R - 0.5 * s for s in sig]
+    counts, centres = _uniform_ball_counts(n_of_type, a_of_type, R, rmax, bins, samples, 31)
+    g, r = oracle.rdf_normalise(counts, centres, n_of_type, sig, R, rmax, bins, n_samples=samples)
+    edges = np.arange(bins + 1) * (rmax / bins)
+    for a in range(2):
+        for b in range(2):
+            for k in range(1, bins):
+                if edges[k + 1] > rmax - 0.5 * sig[b]:
+                    continue
+                sd = 1.0 / math.sqrt(counts[a, b, k])
+                assert abs(g[a, b, k] - 1.0) < 4.5 * sd + 1e-3, (a, b, k, g[a, b, k], sd)
+    assert np.allclose(r, 0.5 * (edges[1:] + edges[:-1]))
