@@ -88,7 +88,9 @@ typedef struct mc_options {
     void* hip_stream;       /* hipStream_t to enqueue on (e.g. a PyTorch stream);
                                NULL = a stream owned by the handle                 */
     int32_t band;           /* look-ahead band width in 64-ion groups (0..4),
-                               -1 = automatic; affects speed only                  */
+                               -1 = automatic; affects speed only.  Clamped to
+                               3 for float chains with per-ion diameters and
+                               for the delayed-acceptance kernel               */
     int32_t waves;          /* waves per workgroup (4 or 8), 0 = automatic         */
     int32_t workgroups;     /* workgroups serving the chain, 0 = automatic         */
     int64_t trace_moves;    /* record accept bit and dE of the first this many
@@ -141,7 +143,11 @@ int mc_create(int32_t n, const double* charges, const double* diameters,
  * with the same seed is identical to one run in a single call.  The energy
  * re-sum and g(r) sampling of the options are interleaved at sweep counts
  * that are multiples of their intervals.  Asynchronous: returns once the work
- * is enqueued; device errors surface on the next synchronising call.
+ * is enqueued; device errors surface on the next synchronising call.  With a
+ * surrogate installed (mc_set_surrogate) and no move log, the call
+ * synchronises once per drift-monitor window to see whether the monitor has
+ * switched every chain to the plain test; from then on it launches the plain
+ * sweep kernel, re-planning the schedule for it.
  */
 int mc_sweep(mc_handle* h, int64_t n_sweeps, uint64_t seed);
 
@@ -255,6 +261,11 @@ typedef struct mc_stats {
     int64_t da_stage2_rejected;  /* of those, rejected by stage 2                  */
     int64_t da_fallback_sweep;   /* sweep of the fall-back to the plain test, -1   */
     double da_last_rate;     /* stage-2 rejection rate of the last monitor window  */
+    int32_t da_kernel;       /* sweep launches run the delayed-acceptance kernel
+                                (a surrogate is installed and on, or moves are
+                                logged); 0 once the monitor has switched every
+                                chain to the plain test                            */
+    int32_t reserved0;
 } mc_stats;
 
 /* Synchronises and fills *out. */
@@ -367,8 +378,11 @@ int mc_plan_schedule(int32_t n_chains, const int32_t* nb, const double* scale, c
                      int32_t* item_chain, int32_t* item_index, int32_t* item_wg, int32_t max_items);
 
 /*
- * Autotuner: runs one launch of calib_sweeps sweeps of every chain (real
- * sweeps that continue the chains, keyed by seed), fits the cost model's a
+ * Autotuner: runs calib_sweeps sweeps of every chain (real sweeps that
+ * continue the chains, keyed by seed, as mc_sweep runs them: launches end at
+ * every re-sum, g(r) and monitor interval boundary, and the re-sums and
+ * samples due there are taken), sums each chain's device time over those
+ * launches, fits the cost model's a
  * and b to the measured per-chain times by least squares on relative error
  * (a held within [0.3, 4] us), and gives each chain a factor: its measured
  * time over the model's prediction.  It then re-plans for the smallest

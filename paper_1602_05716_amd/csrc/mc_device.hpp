@@ -14,6 +14,7 @@ constexpr int kGroup = 64;   // movers per group = lanes of one wavefront
 constexpr int kRing = 1024;  // group records kept per chain
 constexpr int kMaxBand = 4;  // largest look-ahead band, in groups
 constexpr int kDaMaxBand = 3;  // ... of chains on the delayed-acceptance kernel
+constexpr int kMaxBandPerIon = 3;  // ... of float chains with per-ion diameters
 
 // Per-group record published by the workgroup that decided the group; one
 // 16-byte transaction, so the tag and the accept mask are read together.

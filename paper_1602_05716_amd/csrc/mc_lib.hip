@@ -164,6 +164,7 @@ struct mc_handle {
     double model_a = kModelA, model_b = kModelB;
     bool da_kernel = false;       // sweep launches use the delayed-acceptance kernel
     int da_window = 0;            // monitor window of the installed surrogates (0: none)
+    int64_t da_checked = -1;      // sweep count at the last look at the chains' DAState
     mc_options opt{};
     DeviceInfo dev;
     hipStream_t stream = nullptr;
@@ -768,19 +769,58 @@ int launch_reduction(mc_handle* h, int64_t n_sweeps, uint64_t seed) {
 
 using LaunchFn = int (*)(mc_handle*, int64_t, uint64_t);
 
-int sweep_all(mc_handle* h, int64_t n_sweeps, uint64_t seed, LaunchFn launch = launch_sweeps) {
+// After the drift monitor has switched every chain of the handle to the plain
+// test, the delayed-acceptance kernel (one wave per SIMD, histograms and
+// conflict tests) has nothing left to do: later launches use the plain sweep
+// kernel on a schedule planned for it.  Looked at once per monitor window,
+// before the next launch (a stream synchronisation); the chains' bands are
+// kept, and a move log keeps the delayed-acceptance kernel (it fills the
+// log).
+int leave_da_kernel_if_off(mc_handle* h) {
+    if (!h->da_kernel || h->opt.log_moves > 0 || h->da_window <= 0 || h->da_checked == h->sweeps ||
+        h->sweeps % h->da_window != 0)
+        return MC_OK;
+    h->da_checked = h->sweeps;
+    int rc = sync_check(h);
+    if (rc) return rc;
+    for (Chain& c : h->chains) {
+        int32_t active = 0;
+        HIPCHECK(h, hipMemcpy(&active, &c.da->active, sizeof(active), hipMemcpyDeviceToHost));
+        if (active) return MC_OK;
+    }
+    h->da_kernel = false;
+    std::vector<int> wg;
+    WgLists lists;
+    plan_schedule(h, wg, lists);
+    return apply_schedule(h, wg, lists);
+}
+
+int last_launch_ms(mc_handle* h, std::vector<double>& ms);
+
+// n_sweeps sweeps in launches that end at every re-sum, g(r) and monitor
+// interval boundary, with the re-sums and samples due there.  With
+// chain_ms the device time of every chain is summed over the launches.
+int sweep_all(mc_handle* h, int64_t n_sweeps, uint64_t seed, LaunchFn launch = launch_sweeps,
+              std::vector<double>* chain_ms = nullptr) {
     if (n_sweeps < 0 || h->sweeps + n_sweeps > (int64_t)UINT32_MAX)
         return fail(h, MC_E_ARG, "n_sweeps out of range");
+    if (chain_ms) chain_ms->assign(h->chains.size(), 0.0);
     int64_t left = n_sweeps;
     while (left > 0) {
+        int rc = leave_da_kernel_if_off(h);
+        if (rc) return rc;
         int64_t step = left;
         const int re = h->opt.resum_every, rd = h->opt.rdf_every;
         if (re > 0) step = std::min<int64_t>(step, re - h->sweeps % re);
         if (rd > 0) step = std::min<int64_t>(step, rd - h->sweeps % rd);
         const int dw = h->da_window;  // the drift monitor judges at window ends
         if (dw > 0) step = std::min<int64_t>(step, dw - h->sweeps % dw);
-        int rc = launch(h, step, seed);
-        if (rc) return rc;
+        if ((rc = launch(h, step, seed))) return rc;
+        if (chain_ms) {
+            std::vector<double> ms;
+            if ((rc = last_launch_ms(h, ms))) return rc;
+            for (size_t k = 0; k < ms.size(); ++k) (*chain_ms)[k] += ms[k];
+        }
         left -= step;
         if (re > 0 && h->sweeps % re == 0 && (rc = launch_energy(h, 1, 1))) return rc;
         if (rd > 0 && h->sweeps % rd == 0 && (rc = launch_rdf(h))) return rc;
@@ -806,6 +846,9 @@ int create_handle(int32_t n_chains, const mc_chain_spec* specs, const mc_options
         setup_chain(h->chains[k], specs[k], opt);
         h->uniform_sigma = h->uniform_sigma && h->chains[k].uniform_sigma;
     }
+    // the float kernel for per-ion diameters holds fewer band groups
+    if (!h->fp64 && !h->uniform_sigma)
+        for (Chain& c : h->chains) c.band = std::min(c.band, kMaxBandPerIon);
 
     int rc = MC_OK;
     auto bail = [&](int code) {
@@ -1213,6 +1256,7 @@ int chain_stats(mc_handle* h, int32_t ci, mc_stats* out) {
     out->da_stage2_rejected = (int64_t)st[ST_DA_S2REJ];
     out->da_fallback_sweep = ds.fallback_sweep;
     out->da_last_rate = ds.last_rate;
+    out->da_kernel = h->da_kernel ? 1 : 0;
     return MC_OK;
 }
 
@@ -1824,11 +1868,11 @@ int mc_autotune(mc_handle* h, int32_t calib_sweeps, uint64_t seed, double* model
     if (calib_sweeps < 1 || calib_sweeps > kMaxLaunchSweeps)
         return fail(h, MC_E_ARG, "calib_sweeps must be in [1, 4096]");
     if (h->failed) return fail(h, MC_E_STATE, "handle is in a failed state: " + h->err);
-    // one calibration launch (real sweeps of every chain) on the current schedule
-    int rc = launch_sweeps(h, calib_sweeps, seed);
-    if (rc) return rc;
+    // calibration sweeps (real sweeps of every chain, with the re-sums, g(r)
+    // samples and monitor checks that fall due) on the current schedule
     std::vector<double> ms;
-    if ((rc = last_launch_ms(h, ms))) return rc;
+    int rc = sweep_all(h, calib_sweeps, seed, launch_sweeps, &ms);
+    if (rc) return rc;
     // least squares, relative error: t_c / S = a nb_c + b nb_c^2 / w_c (microseconds)
     double s11 = 0, s12 = 0, s22 = 0, r1 = 0, r2 = 0;
     int used = 0;
@@ -1892,9 +1936,7 @@ int mc_autotune(mc_handle* h, int32_t calib_sweeps, uint64_t seed, double* model
     std::vector<int> wg;
     WgLists lists;
     plan_schedule(h, wg, lists);
-    if ((rc = apply_schedule(h, wg, lists))) return rc;
-    if (h->opt.resum_every > 0 && h->sweeps % h->opt.resum_every == 0 && (rc = launch_energy(h, 1, 1))) return rc;
-    return MC_OK;
+    return apply_schedule(h, wg, lists);
 }
 
 int mc_set_surrogate(mc_handle* h, int32_t chain, const double* params, double ref_stage2_reject,

@@ -222,6 +222,11 @@ template <> struct SliceBits<16> { using type = uint16_t; };
 // per CU and take three.  The delayed-acceptance kernels, whose LDS also
 // holds the neighbour histograms and the network, take one.)
 template <bool DA> constexpr int kBandSlots = DA ? kDaMaxBand : kMaxBand;
+// ... and of the float kernel for per-ion diameters, whose extra per-partner
+// work leaves no registers for a fourth band group (it would spill, and a
+// spilling persistent kernel runs one workgroup per CU)
+template <typename T, bool UNIFORM_SIGMA, bool DA>
+constexpr int kChainBand = (!DA && !UNIFORM_SIGMA && sizeof(T) == 4) ? kMaxBandPerIon : kBandSlots<DA>;
 template <typename T, int M, bool DA>
 constexpr int kChainSlots = DA ? 1 : (sizeof(T) == 4 ? 2 : 3);
 // A compute wave waiting for a partner group more than this many groups
@@ -918,8 +923,9 @@ __device__ __forceinline__ void sweep_chain(SweepShared<T, M, DA>& sh, const Cha
     using T4 = typename Prec<T>::T4;
     using IO = PosIO<T>;
     constexpr int P = kGroup / M;
-    constexpr int KB = SweepShared<T, M, DA>::KB;
+    constexpr int KB = kChainBand<T, UNIFORM_SIGMA, DA>;
     constexpr int LC = SweepShared<T, M, DA>::LC;
+    static_assert(KB >= LC, "the chain step's band slots are band groups");
     using SB = typename SliceBits<P>::type;
 
     const int lane = threadIdx.x & 63;

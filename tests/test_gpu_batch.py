@@ -220,3 +220,32 @@ def test_ensemble_sampled_chains_fp32(oracle):
             ev = mask == 1
             err = np.abs(de[ev] - rp["dE"][ev]) / np.maximum(np.abs(rp["dE"][ev]), 1.0)
             assert err.max() <= TOL32, (k, err.max())
+
+
+def test_autotune_calibration_keeps_the_interval_work(oracle):
+    """The autotuner's calibration sweeps run as mc_sweep runs them: a
+    calibration that crosses a re-sum boundary takes that re-sum (the
+    running energy is reset to the double re-sum there), and the chains
+    continue bit-exactly."""
+    from paper_1602_05716_amd import mc
+    systems, D = _mixed_batch()
+    systems, D = systems[1:4], D[1:4]
+    seed = 0xA770
+    cap = max(sy.n for sy in systems) * 9
+    _say("autotune across a re-sum boundary, sizes=%s" % [sy.n for sy in systems])
+    with mc.Batch(systems, max_disp=[0.5 * d for d in D], precision="fp64", trace_moves=cap,
+                  resum_every=5) as b:
+        b.sweep(3, seed)
+        b.autotune(4, seed)  # sweeps 3..6: crosses the re-sum at sweep 5
+        for k in range(len(systems)):
+            assert b.stats(k)["resums"] == 1, k
+        b.sweep(2, seed)
+        for k, sy in enumerate(systems):
+            st = b.stats(k)
+            assert st["sweeps"] == 9 and st["resums"] == 1, (k, st)
+            acc, de = b.trace(k, 9 * sy.n)
+            ref, r = _oracle_run(oracle, sy, D[k], seed, k, 9, 9 * sy.n)  # chain id k
+            assert np.array_equal(acc, r["acc"]), k
+            assert np.array_equal(b.positions(k), ref.x), k
+            e_run, e_ex = b.energy(k, exact=True)
+            assert abs(e_run - e_ex) <= 1e-9 * max(1.0, abs(e_ex)), k

@@ -83,11 +83,17 @@ def _check_da(oracle, sy, precision, sweeps, seed, D, params, da_on=True, tol_de
     band_tol = 1e-6 if tol_de is None else 2 * TOL32
     for k in dis:
         fl = int(r["flags"][k])
+        # the wall test is the same double arithmetic on both sides
+        assert not fl & 1, ("wall decision differs", int(k))
         near = abs(r["dE"][k] - thr3[k]) <= band_tol * max(1.0, abs(r["dE"][k]))
         if da_on and not conflict[k]:
             near = (abs(r["dEh"][k] - thr3[k]) <= 1e-3 * (1.0 + abs(thr3[k])) or
                     abs(r["dE"][k] - r["dEh"][k] - thr2[k]) <= 1e-3 * (1.0 + abs(thr2[k])))
-        assert near or (fl & 3), ("decision differs away from a threshold", int(k), fl)
+        near = near and not fl & 2
+        # an overlap decision may differ only for a trial at contact within
+        # float rounding of sigma_ij (float path)
+        at_contact = f32 and abs(r["margin"][k]) <= 1e-6
+        assert near or at_contact, ("decision differs away from a threshold", int(k), fl, r["margin"][k])
     assert dis.size <= max(2, n_moves // 2000)
     return st, r, lg
 
@@ -147,27 +153,32 @@ def test_plain_mode_logging_matches_oracle(oracle):
     assert st["da_active"] == 0 and np.all(lg["dEh"] == 0.0)
 
 
-def test_drift_monitor_falls_back(oracle):
+@pytest.mark.parametrize("band", [1, 3])
+def test_drift_monitor_falls_back(oracle, band):
     """A reference rate of 0 with delta 0: the first window with a stage-2
-    rejection switches the chain to the plain test from the next window on;
-    the moves before and after follow the oracle's DA and plain chains."""
+    rejection switches the chain to the plain test from the next window on,
+    and the library then launches the plain sweep kernel; the moves before
+    and after follow the oracle's DA and plain chains."""
     from paper_1602_05716_amd import mc
     sy = _sys(1024, 0.05, 0.8, seed=44)
     p = _params(9, 0.2)
     D, seed, sweeps = 2.0, 0xFA11, 4
     n_moves = sweeps * sy.n
+    _say("fall-back band %d" % band)
     with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision="fp64", max_disp=0.5 * D,
                   trace_moves=n_moves, resum_every=0, waves=4, da_window=2, da_delta=0.0, da_rcut=1.5,
-                  band=1) as ch:
+                  band=band) as ch:
         ch.set_surrogate(p, 0.0, True)
+        assert ch.stats()["da_kernel"] == 1
         ch.sweep(sweeps, seed)
         acc, de = ch.trace(n_moves)
         st = ch.stats()
     assert st["da_active"] == 0 and st["da_fallback_sweep"] == 2, st
+    assert st["da_kernel"] == 0 and st["band"] == band, st
     w = 2 * sy.n
-    r1 = oracle.da_run(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, D, seed, 0, 0, w, p, rc=1.5, band=1, da_on=1,
+    r1 = oracle.da_run(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, D, seed, 0, 0, w, p, rc=1.5, band=band, da_on=1,
                        acc_given=acc[:w])
     assert r1["mismatches"] <= 2
-    r2 = oracle.da_run(r1["x"], sy.q, sy.sigma, sy.R, sy.lB, D, seed, 0, 2, n_moves - w, p, rc=1.5, band=1,
+    r2 = oracle.da_run(r1["x"], sy.q, sy.sigma, sy.R, sy.lB, D, seed, 0, 2, n_moves - w, p, rc=1.5, band=band,
                        da_on=0, acc_given=acc[w:])
     assert r2["mismatches"] == 0
