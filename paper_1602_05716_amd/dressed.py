@@ -37,7 +37,7 @@ def _log(*a):
 
 
 def run(n: int, sweeps: int, equil: int, every: int, rmax: float, bins: int, seed: int, chunk: int = 100,
-        margin: float | None = None, debye_A: float = inputs.PAPER_DEBYE_A):
+        margin: float | None = None, debye_A: float = inputs.PAPER_DEBYE_A, trace: bool = False):
     from . import mc
     t0 = time.perf_counter()
     sy = inputs.three_to_one(n, seed, debye_A)
@@ -47,7 +47,8 @@ def run(n: int, sweeps: int, equil: int, every: int, rmax: float, bins: int, see
         margin = 10.0 * sy.meta["kappa_inv"]
     # the handle's own stream: nothing here needs another GPU runtime
     with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision="fp32", max_disp=md, resum_every=100,
-                  rdf_every=every, rdf_bins=bins, rdf_rmax=rmax, rdf_margin=margin) as ch:
+                  rdf_every=every, rdf_bins=bins, rdf_rmax=rmax, rdf_margin=margin,
+                  trace_moves=(equil + sweeps) * n if trace else 0) as ch:
         done = 0
         while done < equil:
             k = min(chunk, equil - done)
@@ -70,6 +71,8 @@ def run(n: int, sweeps: int, equil: int, every: int, rmax: float, bins: int, see
         st = ch.stats()
         es = ch.energy_series(st["sweeps"])[s0:]
         e_run, e_ex = ch.energy(exact=True)
+        if trace:
+            st["trace"] = ch.trace((equil + sweeps) * n)
     types, keys = sy.types()
     n_of_type = np.bincount(types, minlength=len(keys))
     return sy, md, r, st, es, wall, n_of_type, (e_run, e_ex), margin

@@ -79,7 +79,11 @@ def random_start(system: System, seed: int, batch: int = 4096, max_rounds: int =
     smax = float(sig.max()) if n else 1.0
     xyz = np.zeros((n, 3), np.float64)
     placed = 0
-    tree = None
+    # kept ions are indexed by two k-d trees: one over xyz[:big_n], rebuilt
+    # only when the other, over the ions kept since, has grown to a quarter
+    # of it (the candidates tested are the same as with one tree)
+    trees = []
+    big_n = 0
     rounds = 0
     while placed < n:
         rounds += 1
@@ -97,10 +101,13 @@ def random_start(system: System, seed: int, batch: int = 4096, max_rounds: int =
         rad = a * rng.random(m) ** (1.0 / 3.0)
         cand = v * rad[:, None]
         ok = np.ones(m, bool)
-        if tree is not None:
+        for tree, base in trees:
             hits = tree.query_ball_point(cand, r=smax)
-            for k in range(m):
+            for k in np.flatnonzero(np.fromiter(map(len, hits), np.int64, m)):
+                if not ok[k]:
+                    continue
                 for j in hits[k]:
+                    j += base
                     d = np.sqrt(np.sum((cand[k] - xyz[j]) ** 2))
                     if d < 0.5 * (s_here + sig[j]):
                         ok[k] = False
@@ -116,7 +123,12 @@ def random_start(system: System, seed: int, batch: int = 4096, max_rounds: int =
         kept = cand[ok][:need]
         xyz[placed:placed + len(kept)] = kept
         placed += len(kept)
-        tree = cKDTree(xyz[:placed])
+        if placed - big_n > max(batch, big_n // 4):
+            big_n = placed
+            trees = [(cKDTree(xyz[:placed]), 0)]
+        else:
+            trees = trees[:1] if big_n else []
+            trees.append((cKDTree(xyz[big_n:placed]), big_n))
     return xyz
 
 

@@ -96,9 +96,14 @@ def test_production_driver_runs_and_pools(tmp_path):
     from paper_1602_05716_amd import analysis, dressed
     _say("dressed driver N=4096")
     sy, md, r, st, es, wall, n_of_type, (e_run, e_ex), margin = dressed.run(
-        4096, 6, 2, 2, 12.0, 60, 9, chunk=3, debye_A=20.0)
+        4096, 6, 2, 2, 12.0, 60, 9, chunk=3, debye_A=20.0, trace=True)
     assert r["samples"] == 3 and st["sweeps"] == 8 and len(es) == 6
-    assert abs(e_run - e_ex) <= 1e-5 * max(1.0, abs(e_ex))
+    # no re-sum in 8 sweeps: the running energy carries the float error of
+    # every accepted dE, each within the float path's 1e-5 max(|dE|, 1 kT)
+    acc, de = st["trace"]
+    bound = 1e-5 * float(np.sum(np.maximum(np.abs(de[acc == 1]), 1.0)))
+    _say("running minus re-summed energy %.3e kT, bound %.3e kT, |E| %.1f kT" % (e_run - e_ex, bound, abs(e_ex)))
+    assert abs(e_run - e_ex) <= bound
     path = str(tmp_path / "d.npz")
     np.savez(path, counts=r["counts"], centres=r["centres"], samples=r["samples"], g=r["g"], n_of_type=n_of_type,
              R=sy.R, rmax=12.0, bins=60, energy=es, max_disp=md, n=4096, margin=margin)
@@ -106,3 +111,39 @@ def test_production_driver_runs_and_pools(tmp_path):
     assert np.allclose(g, r["g"], rtol=1e-12, atol=0)
     with pytest.raises(ValueError):
         dressed.pooled([path, path], (5.0, 5.1))  # too few bins in the window
+
+
+def test_running_energy_error_is_the_sum_of_move_errors(oracle):
+    """Float path, the 3:-1 system with cube moves of side L / 3: the running
+    energy is the start's double re-sum plus every accepted float dE, the
+    re-sum of the final state the start's plus every accepted exact dE, so
+    their difference is the sum of the per-move float errors (each checked
+    against the exact double dE of the same float state), up to double
+    rounding of the two pair sums."""
+    from scipy.spatial.distance import pdist
+
+    from paper_1602_05716_amd import inputs, mc
+    sy = inputs.three_to_one(4096, 9, 20.0)
+    sweeps, seed, md = 8, 9, sy.R / 3.0
+    n_moves = sweeps * sy.n
+    _say("running-energy error, 3:-1 N=4096, %d sweeps" % sweeps)
+    with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision="fp32", max_disp=md, resum_every=0,
+                  trace_moves=n_moves) as ch:
+        e0 = ch.energy()
+        ch.sweep(sweeps, seed)
+        acc, de = ch.trace(n_moves)
+        e_run, e_ex = ch.energy(exact=True)
+    rp = oracle.replay_f32(sy.xyz.astype(np.float32), sy.q, sy.sigma, sy.R, sy.lB, np.float32(2 * md), seed, 0, 0,
+                           n_moves, acc_given=acc)
+    a = acc == 1
+    err = de - rp["dE"]
+    assert np.max(np.abs(err) / np.maximum(np.abs(rp["dE"]), 1.0)) <= 1e-5
+    x0 = sy.xyz.astype(np.float32).astype(np.float64)
+    x1 = rp["xyz"].astype(np.float64)
+    qq = np.abs(np.outer(sy.q, sy.q))[np.triu_indices(sy.n, 1)]
+    rounding = 1e-12 * sy.lB * (float(np.sum(qq / pdist(x0))) + float(np.sum(qq / pdist(x1))))
+    _say("drift %.3e kT = sum of %d move errors %.3e kT (largest %.2e); |E| %.1f kT" %
+         (e_run - e_ex, int(a.sum()), float(np.sum(err[a])), float(np.max(np.abs(err[a]))), abs(e_ex)))
+    assert abs((e_run - e_ex) - float(np.sum(err[a]))) <= rounding + 1e-12 * float(np.sum(np.abs(de[a])))
+    assert abs((e_ex - e0) - float(np.sum(rp["dE"][a]))) <= rounding + 1e-12 * float(np.sum(np.abs(de[a])))
+

@@ -12,6 +12,9 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-5
+# float rounding of a contact test: the float squared distance of two float
+# positions carries about 3 ulp (2e-7) relative, half that on the distance
+CONTACT_TOL = 1e-6
 
 
 def _sys(n_cat, n_an, q=(1.0, -1.0), s=(1.0, 1.0), phi=0.05, lB=0.7, seed=1):
@@ -108,6 +111,21 @@ def test_fp64_resume_matches_single_call(oracle):
     assert np.array_equal(xa, xb)
 
 
+def _assert_valid_state(x, sy):
+    """Every ion inside its wall radius (exactly: the wall test is double
+    arithmetic on both sides) and no pair closer than sigma_ij beyond float
+    rounding of the contact distance."""
+    from scipy.spatial import cKDTree
+    x = np.asarray(x, np.float64)
+    a = sy.R - 0.5 * sy.sigma
+    assert np.all(np.einsum("ij,ij->i", x, x) <= a * a), "ion outside the wall"
+    pairs = cKDTree(x).query_pairs(float(sy.sigma.max()), output_type="ndarray")
+    if len(pairs):
+        d = np.linalg.norm(x[pairs[:, 0]] - x[pairs[:, 1]], axis=1)
+        sij = 0.5 * (sy.sigma[pairs[:, 0]] + sy.sigma[pairs[:, 1]])
+        assert np.all(d / sij - 1.0 >= -CONTACT_TOL), "overlapping pair in the final state"
+
+
 def _fp32_check(oracle, sy, sweeps, seed, D, sample_every=1, **opts):
     from paper_1602_05716_amd import mc
     n_moves = sweeps * sy.n
@@ -127,17 +145,22 @@ def _fp32_check(oracle, sy, sweeps, seed, D, sample_every=1, **opts):
     d64, d32 = rp["dE"][ev], de[ev]
     err = np.abs(d32 - d64) / np.maximum(np.abs(d64), 1.0)
     assert err.max() <= TOL32, (err.max(), int(np.argmax(err)))
-    # decisions: the GPU's own decision must follow from its own dE; a
-    # disagreement with the oracle is allowed only inside the tolerance band
-    # around the Metropolis threshold or at an overlap/wall boundary case
+    # decisions: a disagreement with the oracle is allowed only inside the
+    # tolerance band around the Metropolis threshold (no wall, no overlap on
+    # the oracle's side) or for a trial at contact within float rounding of
+    # sigma_ij; the wall test is the same double arithmetic on both sides
     own = rp["own"][ev]
     flags = rp["flags"][ev]
+    margin = rp["margin"][ev]
     a = acc[ev]
     dis = np.flatnonzero(a != own)
     thr = -np.log(np.maximum(rp["u3"][ev], 1e-300))
     for k in dis:
-        near = abs(d64[k] - thr[k]) <= TOL32 * max(abs(d64[k]), 1.0)
-        assert near or flags[k] != 0, ("decision differs away from threshold", k, d64[k], thr[k])
+        assert not flags[k] & 1, ("wall decision differs", k)
+        near = not flags[k] & 2 and abs(d64[k] - thr[k]) <= TOL32 * max(abs(d64[k]), 1.0)
+        at_contact = abs(margin[k]) <= CONTACT_TOL
+        assert near or at_contact, ("decision differs away from threshold", k, d64[k], thr[k], margin[k])
+    _assert_valid_state(x, sy)
     return err, dis.size, int(ev.sum())
 
 
@@ -221,10 +244,14 @@ def test_rdf_counts_match_oracle(oracle):
         ch.sweep(2, 8)
         x = ch.positions()
         r = ch.rdf()
-    types, _ = sy.types()
+    types, species = sy.types()
     c, ce = oracle.rdf_counts(x, types, 2, sy.R, 5.0, 50)
     assert r["samples"] == 1
     assert np.array_equal(r["counts"], c) and np.array_equal(r["centres"], ce)
+    n_of_type = np.bincount(types, minlength=2)
+    sig_of_type = [sy.sigma[types == t][0] for t in range(2)]
+    g, _ = oracle.rdf_normalise(c, ce, n_of_type, sig_of_type, sy.R, 5.0, 50)
+    assert np.allclose(r["g"], g, rtol=1e-12, atol=0)
 
 
 def test_rdf_margin_moves_the_centres_inward(oracle):
@@ -243,6 +270,10 @@ def test_rdf_margin_moves_the_centres_inward(oracle):
     c0, ce0 = oracle.rdf_counts(x, types, 2, sy.R, 4.0, 64)
     assert r["samples"] == 1 and ce.sum() < ce0.sum()
     assert np.array_equal(r["counts"], c) and np.array_equal(r["centres"], ce)
+    # normalised by the neighbours' density over the whole sphere, not R - margin
+    n_of_type = np.bincount(types, minlength=2)
+    g, _ = oracle.rdf_normalise(c, ce, n_of_type, [1.0, 1.0], sy.R, 4.0, 64)
+    assert np.allclose(r["g"], g, rtol=1e-12, atol=0)
 
 
 def test_energy_series_and_stats(oracle):
