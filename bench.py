@@ -1,10 +1,11 @@
 """Benchmark: exact-energy sequential Metropolis MC of the 1:1 primitive model
 at N = 32768 on one MI355X.
 
-One step = mc_sweep of --sweeps-per-step sweeps (default 100) of the whole
+One step = mc_sweep of --sweeps-per-step sweeps (default 500) of the whole
 hot path: the persistent sweep kernel (trial draw, exact dE over all N-1
 partners with the hard-core test, sequential accept/reject, in-place update)
-followed by the double-precision energy re-sum that closes the interval.
+with the double-precision energy re-sum every 100 sweeps (five per step; 20
+steps are the 10^4 sweeps of the workload).
 
 Workload: 16384 cations (+1) and 16384 anions (-1), sigma = 1, l_B = 0.7,
 hard-wall sphere at volume fraction 0.05, seeded random start (synthetic),
@@ -29,15 +30,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MC moves/s + pair terms/s at N=32768; ESS/s plain vs batched vs surrogate-DA"
 CUS, CLOCK_HZ = 256, 2.4e9
-# ALU roofline of one pair term (float path).  Algorithmic work per term:
-# two squared distances (3 sub + 3 mul/fma each), the difference of the two
-# inverse distances and its charge-weighted accumulation (2), the contact
-# test (1): 15 vector ALU lane-ops, plus 2 reciprocal square roots.
-# Chip rates: the published FP32 vector peak, 157.3 TFLOP/s = 128 FMA lanes
-# per clock per CU; transcendentals at a quarter of that, 32 lanes per clock
-# per CU (the valu_peak probe measures both on the device).
+# Roofline of the sweep kernel: the reciprocal square roots.  One pair term
+# (float path) is two inverse distances, 2 v_rsq_f32, plus 15 vector ALU
+# lane-ops (two squared distances, 3 sub + 3 mul/fma each; the difference of
+# the inverse distances and its charge-weighted accumulation, 2; the contact
+# test, 1).  frac = 2 x pair terms/s over the v_rsq_f32 rate the valu_peak
+# probe measures on the device (nominal: a quarter of the 128 FMA lanes per
+# clock per CU of the published 157.3 TFLOP/s FP32 peak, 32 lanes).
 VALU_PER_PAIR, RSQ_PER_PAIR = 15, 2
 VALU_LANES_PER_CLK_CU, RSQ_LANES_PER_CLK_CU = 128.0, 32.0
+RSQ_PEAK_NOMINAL = CUS * CLOCK_HZ * RSQ_LANES_PER_CLK_CU
+# the same pair term with the rsq and the other VALU ops issued one after the
+# other (they do not co-issue; packed FP32 is off): the instruction-mix ceiling
 PAIR_PEAK_PER_S = CUS * CLOCK_HZ / (VALU_PER_PAIR / VALU_LANES_PER_CLK_CU + RSQ_PER_PAIR / RSQ_LANES_PER_CLK_CU)
 
 
@@ -92,18 +96,42 @@ def tune_max_disp(chain, max_disp, target=0.40, rounds=8, sweeps=4, seed=0xD15C)
     return md
 
 
-def cpu_baseline(system, D, seed, sweeps=1):
-    """The FP64 oracle, serial, on the same system and start (bounded sample)."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(system, D, seed, sweeps=1, omp_sweeps=2):
+    """The FP64 oracle on the same system and start (bounded samples): serial
+    on one core (the paper's serial-CPU baseline), and its OpenMP build with
+    the partner sum split over all host threads."""
     from oracle import oracle
+    n = system.n
     ch = oracle.Chain(system.xyz, system.q, system.sigma, system.R, system.lB, D, seed=seed)
     t0 = time.perf_counter()
     ch.run(sweeps)
     dt = time.perf_counter() - t0
-    n = system.n
-    return {"value": sweeps * n / dt, "unit": "moves/s", "cores": 1, "kind": "oracle",
-            "pair_terms_per_s": sweeps * n * (n - 1) / dt,
-            "sample": "%d sweep(s) = %d moves of the same N=%d system and start, FP64 oracle, "
-                      "1 thread, %.1f s" % (sweeps, sweeps * n, n, dt)}
+    out = {"value": sweeps * n / dt, "unit": "moves/s", "cores": 1, "kind": "oracle",
+           "pair_terms_per_s": sweeps * n * (n - 1) / dt, "cpu_model": cpu_model(),
+           "sample": "%d sweep(s) = %d moves of the same N=%d system and start, FP64 oracle, "
+                     "1 thread, %.1f s" % (sweeps, sweeps * n, n, dt)}
+    if omp_sweeps > 0:
+        cm = oracle.Chain(system.xyz, system.q, system.sigma, system.R, system.lB, D, seed=seed, threaded=True)
+        t0 = time.perf_counter()
+        cm.run(omp_sweeps)
+        dm = time.perf_counter() - t0
+        out["all_cores"] = {"value": omp_sweeps * n / dm, "unit": "moves/s", "threads": cm.threads,
+                            "pair_terms_per_s": omp_sweeps * n * (n - 1) / dm,
+                            "sample": "%d sweep(s), OpenMP build of the oracle (partner sum over %d threads), "
+                                      "%.1f s" % (omp_sweeps, cm.threads, dm)}
+    return out
 
 
 def run_valu_probe():
@@ -187,6 +215,45 @@ def batched_leg(args, log_fn=None):
             "batched_over_sequential": t_seq / t_batch}
 
 
+def asymmetric_leg(args, rsq_peak):
+    """The size- and charge-asymmetric 2:1 system: N = 98304 (32768 at +2
+    with sigma 1.0, 65536 at -1 with sigma 0.8), l_B 0.7, phi 0.1, float pair
+    terms with double sums, trial cube side 1 (max displacement 0.5); the
+    sweep kernel for per-ion diameters, all three g_ab(r) sampled every 10
+    sweeps.  Timed with HIP events on the chain's stream."""
+    import torch
+    from paper_1602_05716_amd import inputs, mc
+    system = inputs.asymmetric_2to1()
+    n = system.n
+    stream = torch.cuda.Stream()
+    with mc.Chain(system.xyz, system.q, system.sigma, system.R, system.lB, precision="fp32", max_disp=0.5,
+                  resum_every=100, rdf_every=10, rdf_bins=200, rdf_rmax=10.0, record_timing=1,
+                  hip_stream=stream.cuda_stream) as c:
+        c.sweep(args.asym_sweeps // 4, args.seed)  # warm-up launch
+        c.energy()
+        c.timing_reset()
+        st0 = c.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.sweep(args.asym_sweeps, args.seed)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        launches, kernel_ms, kernel_sweeps = c.timing()
+        st = c.stats()
+        r = c.rdf()
+    pairs = args.asym_sweeps * n * (n - 1)
+    pair_rate = kernel_sweeps * n * (n - 1) / (kernel_ms * 1e-3)
+    return {"workload": "2:1, N=98304 (32768 at +2, sigma 1.0; 65536 at -1, sigma 0.8), l_B 0.7, phi 0.1, "
+                        "seeded random start, max displacement 0.5",
+            "kernel": "sweep_kernel<float,%d> (per-ion diameters)" % st["waves"],
+            "sweeps": args.asym_sweeps, "wall_s": wall, "ms_per_sweep": 1e3 * wall / args.asym_sweeps,
+            "moves_per_s": args.asym_sweeps * n / wall, "pair_terms_per_s": pairs / wall,
+            "kernel_pair_terms_per_s": pair_rate,
+            "rsq_frac": 2.0 * pair_rate / rsq_peak, "band": st["band"], "workgroups": st["workgroups"],
+            "acceptance": (st["accepted"] - st0["accepted"]) / max(1, st["moves"] - st0["moves"]),
+            "rdf_samples": r["samples"], "g_pairs": int(r["g"].shape[0] * r["g"].shape[1])}
+
+
 def reduction_leg(chain, args, sweep_rate):
     """The paper's GPU comparison code (Sec. 4): the same chain continued by
     the per-move parallel-reduction scheme, one launch per trial move, after
@@ -233,7 +300,7 @@ def da_leg(args, md):
     plain run, train the network on the GPU, then run the two-stage chain and
     the plain chain from the same state for the same number of sweeps."""
     import torch
-    from paper_1602_05716_amd import analysis, inputs, mc
+    from paper_1602_05716_amd import analysis, inputs, mc, surrogate
     system = inputs.large_fp32()
     n = system.n
     stream = torch.cuda.Stream()
@@ -249,21 +316,28 @@ def da_leg(args, md):
         tr = lg_chain.train_surrogate(n_log, epochs=args.da_epochs, batch=4096, lr=2e-3, seed=7)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
+        # the same held-out moves scored with the non-learned first stage (a
+        # pass with a vanishing learning rate leaves its weights as they are)
+        coul = lg_chain.train_surrogate(n_log, epochs=1, batch=4096, lr=1e-12, seed=7,
+                                        params_in=surrogate.truncated_coulomb_params(4.0))
         x0 = lg_chain.positions()
     out = {"workload": "1:1 N=32768 phi=0.05 l_B=0.7 (the plain benchmark's system), %d logged moves, "
                        "network 128-128-128-1 bfloat16" % n_log,
            "train_s": t_train, "train_loss": [float(v) for v in tr["loss"]], "val_loss": tr["val_loss"],
-           "ref_stage2_reject": tr["ref_stage2_reject"], "sweeps": args.da_sweeps}
+           "ref_stage2_reject": tr["ref_stage2_reject"],
+           "coulomb_ref_stage2_reject": coul["ref_stage2_reject"], "coulomb_val_loss": coul["val_loss"],
+           "sweeps": args.da_sweeps}
     runs = {}
-    for mode in ("plain", "da"):
+    nets = {"da": (tr["params"], tr["ref_stage2_reject"]), "da_coulomb": (coul["params"], coul["ref_stage2_reject"])}
+    for mode in ("plain", "da", "da_coulomb"):
         kw = dict(precision="fp32", max_disp=md, resum_every=100, hip_stream=stream.cuda_stream, rdf_bins=200,
                   rdf_rmax=10.0)
-        if mode == "da":
+        if mode != "plain":
             kw["waves"] = 4
             kw["band"] = args.da_band
         with mc.Chain(x0, system.q, system.sigma, system.R, system.lB, **kw) as c:
-            if mode == "da":
-                c.set_surrogate(tr["params"], tr["ref_stage2_reject"], True)
+            if mode != "plain":
+                c.set_surrogate(nets[mode][0], nets[mode][1], True)
             # first launch out of the timed region; one drift-monitor window
             # (10 sweeps), so that every timed call below is a single launch
             c.sweep(10, seed + 1)
@@ -281,16 +355,42 @@ def da_leg(args, md):
     def rms(a, b):
         return float(np.sqrt(np.mean((a[..., sel] - b[..., sel]) ** 2)))
     ph = runs["plain"]["halves"]
-    out["plain"] = {k: v for k, v in runs["plain"].items() if k in ("wall_s", "ess", "ess_per_s", "moves_per_s", "acceptance")}
-    out["da"] = {k: v for k, v in runs["da"].items() if k in ("wall_s", "ess", "ess_per_s", "moves_per_s", "acceptance")}
-    sd = runs["da"]["stats"]
-    out["da"].update({"stage1_rejected": sd["da_stage1_rejected"], "stage1_passed": sd["da_stage1_passed"],
-                      "stage2_rejected": sd["da_stage2_rejected"], "conflict_moves": sd["da_conflicts"],
-                      "two_stage_moves": sd["da_moves"], "fallback_sweep": sd["da_fallback_sweep"],
-                      "active_at_end": sd["da_active"]})
-    out["g_rms_da_vs_plain"] = rms(runs["da"]["g"], runs["plain"]["g"])
+    keys = ("wall_s", "ess", "ess_per_s", "moves_per_s", "acceptance")
+    sp = runs["plain"]["stats"]
+    moves = max(1, sp["moves"])
+    out["plain"] = {k: v for k, v in runs["plain"].items() if k in keys}
+    out["plain"].update({"rejected_wall": sp["rejected_wall"], "rejected_overlap": sp["rejected_overlap"]})
+    for mode in ("da", "da_coulomb"):
+        out[mode] = {k: v for k, v in runs[mode].items() if k in keys}
+        sd = runs[mode]["stats"]
+        out[mode].update({"stage1_rejected": sd["da_stage1_rejected"], "stage1_passed": sd["da_stage1_passed"],
+                          "stage2_rejected": sd["da_stage2_rejected"], "conflict_moves": sd["da_conflicts"],
+                          "two_stage_moves": sd["da_moves"], "fallback_sweep": sd["da_fallback_sweep"],
+                          "active_at_end": sd["da_active"], "rejected_wall": sd["rejected_wall"],
+                          "rejected_overlap": sd["rejected_overlap"],
+                          "stage2_reject_rate": sd["da_stage2_rejected"] / max(1, sd["da_stage1_passed"]),
+                          "g_rms_vs_plain": rms(runs[mode]["g"], runs["plain"]["g"])})
+    out["g_rms_da_vs_plain"] = out["da"]["g_rms_vs_plain"]
     out["g_rms_plain_half_vs_half"] = rms(ph[0]["g"], ph[1]["g"])
     out["ess_per_s_da_over_plain"] = out["da"]["ess_per_s"] / out["plain"]["ess_per_s"]
+    out["ess_per_s_coulomb_over_plain"] = out["da_coulomb"]["ess_per_s"] / out["plain"]["ess_per_s"]
+    # What a kernel that skipped the exact work of moves rejected early (with
+    # survivor compaction, which this kernel does not do) could gain at most:
+    # the fraction of moves that would still need the exact pair sum.  Wall
+    # rejections are known from the trial position alone; overlap rejections
+    # by an exact cell-list test (non-learned); stage-1 rejections of moves
+    # without a conflict by the learned first stage.
+    sd = runs["da"]["stats"]
+    wall_f = sp["rejected_wall"] / moves
+    ov_f = sp["rejected_overlap"] / moves
+    s1_f = sd["da_stage1_rejected"] / max(1, sd["moves"])
+    out["exact_work_bound"] = {
+        "plain": 1.0,
+        "wall_prerejection": 1.0 - wall_f,
+        "wall_and_overlap_prerejection": 1.0 - wall_f - ov_f,
+        "learned_stage1_and_prerejection_at_least": 1.0 - wall_f - ov_f - s1_f,
+        "note": "fractions of moves needing the exact O(N) sum; ideal speed-up = 1 / fraction, before the cost "
+                "of compaction and of the lower acceptance of the two-stage chain"}
     return out
 
 
@@ -299,14 +399,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--sweeps-per-step", type=int, default=100)
+    ap.add_argument("--sweeps-per-step", type=int, default=500)
     ap.add_argument("--seed", type=int, default=0x5EED0002)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=1)
+    ap.add_argument("--cpu-omp-sweeps", type=int, default=2,
+                    help="sweeps of the oracle's OpenMP build on all host threads (0: skip)")
     ap.add_argument("--no-probe", action="store_true", help="skip the VALU issue-rate probe")
     ap.add_argument("--band", type=int, default=-1)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--no-asym", action="store_true", help="skip the 2:1 N=98304 leg")
+    ap.add_argument("--asym-sweeps", type=int, default=40)
     ap.add_argument("--batch-sweeps", type=int, default=1000)
     ap.add_argument("--seq-sweeps", type=int, default=20)
     ap.add_argument("--no-da", action="store_true", help="skip the surrogate delayed-acceptance leg")
@@ -337,7 +441,7 @@ def main():
     system = inputs.large_fp32()
     n = system.n
     chain = mc.Chain(system.xyz, system.q, system.sigma, system.R, system.lB, precision="fp32",
-                     max_disp=0.5, resum_every=args.sweeps_per_step, record_timing=1,
+                     max_disp=0.5, resum_every=100, record_timing=1,
                      hip_stream=stream.cuda_stream, band=args.band, waves=args.waves)
     md = tune_max_disp(chain, 0.5)
     log("frozen max_disp %.4f" % md)
@@ -370,22 +474,41 @@ def main():
     # dominant kernel: the persistent sweep kernel, timed by HIP events on its stream
     avg_launch_s = kernel_ms * 1e-3 / max(1, launches)
     per_launch_pairs = (kernel_sweeps / max(1, launches)) * n * (n - 1)
-    achieved = per_launch_pairs / avg_launch_s / 1e12
-    peak = PAIR_PEAK_PER_S / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tpairterm/s",
+    pair_rate = per_launch_pairs / avg_launch_s
+    probe = None if args.no_probe else run_valu_probe()
+    rsq_peak = probe["rsq_per_s"] if probe else RSQ_PEAK_NOMINAL
+    achieved = RSQ_PER_PAIR * pair_rate / 1e12
+    peak = rsq_peak / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T v_rsq_f32/s",
                 "frac": achieved / peak, "traffic": traffic_per_launch(kernel_sweeps / max(1, launches)),
-                "per_unit": "pair term = %d VALU + %d rsq lane-ops" % (VALU_PER_PAIR, RSQ_PER_PAIR),
-                "rsq_only_frac": achieved * RSQ_PER_PAIR / (CUS * CLOCK_HZ * RSQ_LANES_PER_CLK_CU / 1e12),
+                "per_unit": "pair term = %d v_rsq_f32 (+ %d other VALU lane-ops)" % (RSQ_PER_PAIR, VALU_PER_PAIR),
+                "peak_source": "v_rsq_f32 rate measured by the valu_peak probe" if probe else
+                               "nominal 32 rsq lanes per clock per CU at 2.4 GHz",
+                "pair_terms_per_s": pair_rate,
                 "kernel": "sweep_kernel<float,%d>" % st1["waves"],
                 "avg_launch_ms": avg_launch_s * 1e3, "launches": launches,
                 "sweeps_per_launch": kernel_sweeps / max(1, launches)}
+    # the instruction-mix ceiling: rsq and the other VALU ops issued one after
+    # the other, at the nominal and at the probe's measured lane rates
+    mix = {"pair_peak_nominal": PAIR_PEAK_PER_S / 1e12, "frac_nominal": pair_rate / PAIR_PEAK_PER_S,
+           "rsq_frac_attainable_nominal": RSQ_PER_PAIR * PAIR_PEAK_PER_S / RSQ_PEAK_NOMINAL, "unit": "Tpairterm/s"}
+    if probe:
+        clk_per_pair = (VALU_PER_PAIR / probe["fma_lanes_per_clk_cu"] +
+                        RSQ_PER_PAIR / probe["rsq_lanes_per_clk_cu"])
+        pair_peak_probe = CUS * CLOCK_HZ / clk_per_pair
+        mix.update({"pair_peak_probe": pair_peak_probe / 1e12, "frac_probe": pair_rate / pair_peak_probe,
+                    "rsq_frac_attainable_probe": RSQ_PER_PAIR * pair_peak_probe / rsq_peak})
+        roofline["probe"] = probe
+    roofline["instruction_mix_ceiling"] = mix
     reduction = None
     if not args.no_reduction:
         log("per-move parallel-reduction leg (%d sweep(s))" % args.reduction_sweeps)
         reduction = reduction_leg(chain, args, moves / elapsed)
-    probe = None if args.no_probe else run_valu_probe()
-    if probe:
-        roofline["probe"] = probe
+
+    asym = None
+    if not args.no_asym:
+        log("2:1 N=98304 leg (%d sweeps)" % args.asym_sweeps)
+        asym = asymmetric_leg(args, rsq_peak)
 
     batched = None
     if not args.no_batched:
@@ -400,9 +523,11 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("timing the CPU oracle (%d sweep(s))" % args.cpu_sweeps)
-        cpu = cpu_baseline(system, 2.0 * md, args.seed, args.cpu_sweeps)
+        cpu = cpu_baseline(system, 2.0 * md, args.seed, args.cpu_sweeps, args.cpu_omp_sweeps)
         cpu["cores_available"] = os.cpu_count()
         cpu["gpu_over_cpu"] = (moves / elapsed) / cpu["value"]
+        if "all_cores" in cpu:
+            cpu["all_cores"]["gpu_over_cpu"] = (moves / elapsed) / cpu["all_cores"]["value"]
 
     out = {
         "metric": METRIC, "value": moves / elapsed, "unit": "moves/s", "n_gpus": 1,
@@ -422,6 +547,7 @@ def main():
                       "surrogate_da": da["da"]["ess_per_s"] if da else None,
                       "plain_same_run_as_da": da["plain"]["ess_per_s"] if da else None},
         "batched": batched,
+        "asymmetric_2to1": asym,
         "surrogate_da": da,
         "reduction_scheme": reduction,
         "energy": {"tau_int_sweeps": tau, "e_running": e_run, "e_resum": e_exact,

@@ -6,8 +6,10 @@ library's kernels.  Importing this module loads the library and raises
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -54,7 +56,7 @@ class Stats(ctypes.Structure):
                 ("da_active", ctypes.c_int32), ("da_moves", ctypes.c_int64), ("da_conflicts", ctypes.c_int64),
                 ("da_stage1_rejected", ctypes.c_int64), ("da_stage1_passed", ctypes.c_int64),
                 ("da_stage2_rejected", ctypes.c_int64), ("da_fallback_sweep", ctypes.c_int64),
-                ("da_last_rate", ctypes.c_double)]
+                ("da_last_rate", ctypes.c_double), ("da_kernel", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -76,7 +78,8 @@ SYMBOLS = ["mc_options_init", "mc_create", "mc_sweep", "mc_sweep_reduction", "mc
            "mc_create_batch", "mc_chain_count", "mc_chain_energy", "mc_chain_rdf", "mc_chain_species",
            "mc_chain_positions", "mc_chain_trace", "mc_chain_energy_series", "mc_chain_stats",
            "mc_chain_set_max_disp", "mc_get_schedule", "mc_set_schedule", "mc_chain_launch_ms",
-           "mc_autotune", "mc_plan_schedule", "mc_set_surrogate", "mc_get_log", "mc_mlp_grad", "mc_train_surrogate",
+           "mc_autotune", "mc_plan_schedule", "mc_set_surrogate", "mc_get_log", "mc_mlp_grad",
+           "mc_train_surrogate",
            "mc_destroy", "mc_last_error"]
 
 DA_NPARAM = 33153
@@ -146,12 +149,25 @@ def load(path: str = LIB_PATH):
 
 
 _lib = None
+# handles still open: destroyed (their streams synchronised, their device
+# memory freed) before the interpreter's own teardown, so that no HIP object
+# of the library outlives the runtime's exit handlers
+_live = weakref.WeakSet()
+
+
+def _close_live():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def lib():
     global _lib
     if _lib is None:
         _lib = load()
+        atexit.register(_close_live)
     return _lib
 
 
@@ -210,6 +226,7 @@ class Chain:
         if rc != MC_OK:
             raise MCError(rc, self._L.mc_last_error(None).decode())
         self.h = h
+        _live.add(self)
 
     def _check(self, rc):
         if rc != MC_OK:
@@ -241,6 +258,7 @@ class Chain:
         if rc != MC_OK:
             raise MCError(rc, self._L.mc_last_error(None).decode())
         self.h = h
+        _live.add(self)
         return self
 
     def energy(self, exact=False):
@@ -366,6 +384,7 @@ class Batch:
         if rc != MC_OK:
             raise MCError(rc, self._L.mc_last_error(None).decode())
         self.h = h
+        _live.add(self)
         self.count = len(systems)
 
     def _check(self, rc):
@@ -446,6 +465,7 @@ class Batch:
         if rc != MC_OK:
             raise MCError(rc, self._L.mc_last_error(None).decode())
         self.h = h
+        _live.add(self)
         return self
 
     def set_max_disp(self, c, v):
