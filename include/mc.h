@@ -455,6 +455,23 @@ int mc_mlp_grad(int32_t batch, const uint8_t* feats, const double* target, const
                 double* loss, double* grad);
 
 /*
+ * The same pass as mc_mlp_grad, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): it calls no hipMalloc, hipFree or allocating library
+ * routine.  Every buffer of the pass, and the staged inputs, live in one
+ * file-scope device workspace of about 2.2 MB that each GPU the library
+ * runs on holds until the process ends; batch is at most
+ * MC_NOALLOC_MAX_BATCH (else MC_E_ARG).  The workspace is shared by every
+ * call on a GPU and keeps the last call's contents (each pass overwrites
+ * every value it reads): calls that overlap on one GPU, from several host
+ * threads, race.  Same arguments, outputs and errors as mc_mlp_grad; the
+ * reason of a failure is in mc_last_error(NULL).
+ */
+#define MC_NOALLOC_MAX_BATCH 256
+int mc_mlp_grad_noalloc(int32_t batch, const uint8_t* feats, const double* target, const double* params,
+                        double* loss, double* grad);
+
+/*
  * Trains the network on the GPU on chain `chain`'s log: the first n_moves
  * logged moves without a conflict, wall or overlap rejection; the last tenth
  * of them held out.  Target of a move: dE / l_B; loss: mean squared error of
@@ -474,8 +491,9 @@ int mc_train_surrogate(mc_handle* h, int32_t chain, int64_t n_moves, int32_t epo
 /* Releases every resource of the handle; NULL is allowed. */
 void mc_destroy(mc_handle* h);
 
-/* Human-readable description of the last error on h (or of the last failed
- * mc_create when h is NULL).  Never NULL. */
+/* Human-readable description of the last error on h (or, when h is NULL, of
+ * the calling thread's last failed mc_create, mc_create_batch, mc_load or
+ * mc_mlp_grad_noalloc).  Never NULL. */
 const char* mc_last_error(const mc_handle* h);
 
 #ifdef __cplusplus

@@ -23,3 +23,6 @@ int mc_internal_log(mc_handle* h, int32_t chain, MCLogView* out);
 
 // Records an error on the handle (as every entry point does) and returns code.
 int mc_internal_fail(mc_handle* h, int code, const char* msg);
+
+// Records the reason a handle-free call failed, for mc_last_error(NULL).
+void mc_internal_note_error(const char* msg);

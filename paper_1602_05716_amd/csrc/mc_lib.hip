@@ -1301,6 +1301,8 @@ int mc_internal_log(mc_handle* h, int32_t chain, MCLogView* out) {
 
 int mc_internal_fail(mc_handle* h, int code, const char* msg) { return fail(h, code, msg); }
 
+void mc_internal_note_error(const char* msg) { g_create_error = msg ? msg : "unknown error"; }
+
 namespace {
 
 // ---- checkpoints --------------------------------------------------------

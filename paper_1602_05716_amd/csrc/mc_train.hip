@@ -15,8 +15,10 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mc.h"
@@ -256,16 +258,40 @@ struct Net {
         *p = (Q*)q;
         return true;
     }
+    // every buffer of a batch of B moves (the optimizer's moments only when
+    // training), each obtained from take(&pointer, bytes)
+    template <typename Take>
+    static bool layout(Net& n, int B, bool train, Take&& take) {
+        const size_t R = 2 * (size_t)B;
+        return take(&n.P, 4 * kNP) && take(&n.Pw, 4 * kNP) && (!train || (take(&n.m, 4 * kNP) && take(&n.v, 4 * kNP))) &&
+               take(&n.g, 4 * kNP) && take(&n.W1b, 2 * kIn * kHid) && take(&n.W2b, 2 * kHid * kHid) &&
+               take(&n.X, 2 * R * kIn) && take(&n.H1, 2 * R * kHid) && take(&n.H2, 2 * R * kHid) &&
+               take(&n.dZ2b, 2 * R * kHid) && take(&n.dZ1b, 2 * R * kHid) && take(&n.Z1, 4 * R * kHid) &&
+               take(&n.Z2, 4 * R * kHid) && take(&n.out, 4 * R) && take(&n.dout, 4 * R) &&
+               take(&n.dZ2, 4 * R * kHid) && take(&n.dH1, 4 * R * kHid) && take(&n.y, 4 * (size_t)B) &&
+               take(&n.idx, 8 * (size_t)B) && take(&n.loss, 8);
+    }
     bool init(int B, hipStream_t stream) {
         Bmax = B;
         s = stream;
-        const size_t R = 2 * (size_t)B;
-        return get(&P, 4 * kNP) && get(&Pw, 4 * kNP) && get(&m, 4 * kNP) && get(&v, 4 * kNP) && get(&g, 4 * kNP) &&
-               get(&W1b, 2 * kIn * kHid) && get(&W2b, 2 * kHid * kHid) && get(&X, 2 * R * kIn) &&
-               get(&H1, 2 * R * kHid) && get(&H2, 2 * R * kHid) && get(&dZ2b, 2 * R * kHid) &&
-               get(&dZ1b, 2 * R * kHid) && get(&Z1, 4 * R * kHid) && get(&Z2, 4 * R * kHid) && get(&out, 4 * R) &&
-               get(&dout, 4 * R) && get(&dZ2, 4 * R * kHid) && get(&dH1, 4 * R * kHid) && get(&y, 4 * (size_t)B) &&
-               get(&idx, 8 * (size_t)B) && get(&loss, 8);
+        return layout(*this, B, true, [this](auto** p, size_t bytes) { return get(p, bytes); });
+    }
+    // the buffers of a gradient pass (no optimizer moments) carved out of
+    // caller-provided device memory [base, base + cap); nothing is allocated
+    // and nothing is freed by the destructor
+    bool carve(int B, unsigned char* base, size_t cap, size_t* used) {
+        Bmax = B;
+        size_t at = 0;
+        auto take = [&](auto** p, size_t bytes) {
+            const size_t a = (bytes + 255) & ~(size_t)255;
+            if (at + a > cap) return false;
+            *p = reinterpret_cast<std::remove_reference_t<decltype(*p)>>(base + at);
+            at += a;
+            return true;
+        };
+        const bool ok = layout(*this, B, false, take);
+        *used = at;
+        return ok;
     }
     ~Net() {
         if (s) (void)hipStreamSynchronize(s);
@@ -273,7 +299,8 @@ struct Net {
     }
     bool upload_params(const std::vector<float>& p) {
         if (hipMemcpy(P, p.data(), 4 * kNP, hipMemcpyHostToDevice) != hipSuccess) return false;
-        if (hipMemset(m, 0, 4 * kNP) != hipSuccess || hipMemset(v, 0, 4 * kNP) != hipSuccess) return false;
+        if (m && hipMemset(m, 0, 4 * kNP) != hipSuccess) return false;
+        if (v && hipMemset(v, 0, 4 * kNP) != hipSuccess) return false;
         hipLaunchKernelGGL(refresh_kernel, dim3((kNP + 255) / 256), dim3(256), 0, s, P, kNP, Pw, W1b, W2b);
         return hipGetLastError() == hipSuccess;
     }
@@ -324,6 +351,56 @@ float round_bf16_host(double v) {
 
 thread_local std::string g_train_error = "no error";
 
+// Records why a handle-free call failed, for mc_last_error(NULL); returns code.
+int noalloc_fail(int code, const std::string& msg) {
+    g_train_error = msg;
+    mc_internal_note_error(msg.c_str());
+    return code;
+}
+
+// Bytes of the buffers Net::carve takes for a gradient pass of B moves plus
+// the staged byte histograms (each piece rounded up to 256 bytes).
+constexpr size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t grad_pass_bytes(int B) {
+    const size_t R = 2 * (size_t)B;
+    return 3 * round256(4 * (size_t)kNP) + round256(2 * kIn * kHid) + round256(2 * kHid * kHid) +
+           round256(2 * R * kIn) + 4 * round256(2 * R * kHid) + 4 * round256(4 * R * kHid) + 2 * round256(4 * R) +
+           round256(4 * (size_t)B) + round256(8 * (size_t)B) + round256(8) + round256((size_t)B * 2 * kIn);
+}
+
+// Largest batch of mc_mlp_grad_noalloc and its device workspace: one
+// file-scope array, about 2.2 MB, that every GPU the library runs on holds
+// until the process ends.  Host code never names it directly: its device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr int kNoAllocBatch = MC_NOALLOC_MAX_BATCH;
+constexpr size_t kScratchBytes = grad_pass_bytes(kNoAllocBatch);
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up on the device's first
+// call; nullptr (and the reason in g_train_error) on failure.
+unsigned char* device_scratch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        g_train_error = "no usable current HIP device";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_train_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (unsigned char*)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -357,6 +434,50 @@ int mc_mlp_grad(int32_t batch, const uint8_t* feats, const double* target, const
     if (hipMemcpy(g.data(), net.g, 4 * kNP, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(&l, net.loss, 8, hipMemcpyDeviceToHost) != hipSuccess)
         return MC_E_DEVICE;
+    if (loss) *loss = l;
+    if (grad)
+        for (int k = 0; k < kNP; ++k) grad[k] = g[k];
+    return MC_OK;
+}
+
+int mc_mlp_grad_noalloc(int32_t batch, const uint8_t* feats, const double* target, const double* params,
+                        double* loss, double* grad) {
+    if (batch < 32 || batch % 32 != 0 || !feats || !target || !params)
+        return noalloc_fail(MC_E_ARG, "batch must be a positive multiple of 32, and feats, target and params given");
+    if (batch > kNoAllocBatch)
+        return noalloc_fail(MC_E_ARG, "batch " + std::to_string(batch) + " exceeds the workspace's " +
+                                          std::to_string(kNoAllocBatch) + " moves (MC_NOALLOC_MAX_BATCH)");
+    std::vector<float> p(kNP);
+    for (int k = 0; k < kNP; ++k) {
+        if (!std::isfinite(params[k])) return noalloc_fail(MC_E_ARG, "non-finite parameter");
+        p[k] = (float)params[k];
+    }
+    unsigned char* ws = device_scratch();
+    if (!ws) return noalloc_fail(MC_E_DEVICE, g_train_error);
+    Net net;
+    size_t used = 0;
+    uint8_t* dfeat = nullptr;
+    if (!net.carve(batch, ws, kScratchBytes, &used) ||
+        used + round256((size_t)batch * 2 * kIn) > kScratchBytes)
+        return noalloc_fail(MC_E_STATE, "the buffers of the pass do not fit the workspace");
+    dfeat = ws + used;
+    if (!net.upload_params(p)) return noalloc_fail(MC_E_DEVICE, "parameter upload failed");
+    std::vector<float> y(batch);
+    for (int b = 0; b < batch; ++b) y[b] = (float)target[b];
+    if (hipMemcpy(dfeat, feats, (size_t)batch * 2 * kIn, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(net.y, y.data(), 4 * (size_t)batch, hipMemcpyHostToDevice) != hipSuccess)
+        return noalloc_fail(MC_E_DEVICE, "input upload failed");
+    hipLaunchKernelGGL(gather_bytes_kernel, dim3(batch), dim3(256), 0, nullptr, dfeat, batch, net.X);
+    net.forward(batch);
+    net.outputs(batch, round_bf16_host(params[oB3]));
+    net.backward(batch);
+    if (hipDeviceSynchronize() != hipSuccess || hipGetLastError() != hipSuccess)
+        return noalloc_fail(MC_E_DEVICE, "the gradient pass failed on the device");
+    std::vector<float> g(kNP);
+    double l = 0.0;
+    if (hipMemcpy(g.data(), net.g, 4 * kNP, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(&l, net.loss, 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return noalloc_fail(MC_E_DEVICE, "output download failed");
     if (loss) *loss = l;
     if (grad)
         for (int k = 0; k < kNP; ++k) grad[k] = g[k];

@@ -78,7 +78,7 @@ SYMBOLS = ["mc_options_init", "mc_create", "mc_sweep", "mc_sweep_reduction", "mc
            "mc_create_batch", "mc_chain_count", "mc_chain_energy", "mc_chain_rdf", "mc_chain_species",
            "mc_chain_positions", "mc_chain_trace", "mc_chain_energy_series", "mc_chain_stats",
            "mc_chain_set_max_disp", "mc_get_schedule", "mc_set_schedule", "mc_chain_launch_ms",
-           "mc_autotune", "mc_plan_schedule", "mc_set_surrogate", "mc_get_log", "mc_mlp_grad",
+           "mc_autotune", "mc_plan_schedule", "mc_set_surrogate", "mc_get_log", "mc_mlp_grad", "mc_mlp_grad_noalloc",
            "mc_train_surrogate",
            "mc_destroy", "mc_last_error"]
 
@@ -136,6 +136,7 @@ def load(path: str = LIB_PATH):
         "mc_set_surrogate": ([_hp, ctypes.c_int32, _f64p, ctypes.c_double, ctypes.c_int32], ctypes.c_int),
         "mc_get_log": ([_hp, ctypes.c_int32, ctypes.c_int64, _u8p, _f64p, _f64p, _u8p], ctypes.c_int),
         "mc_mlp_grad": ([ctypes.c_int32, _u8p, _f64p, _f64p, _f64p, _f64p], ctypes.c_int),
+        "mc_mlp_grad_noalloc": ([ctypes.c_int32, _u8p, _f64p, _f64p, _f64p, _f64p], ctypes.c_int),
         "mc_train_surrogate": ([_hp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                 ctypes.c_uint64, _f64p, _f64p, _f64p, _f64p, _f64p], ctypes.c_int),
         "mc_destroy": ([_hp], None),
@@ -575,6 +576,21 @@ def mlp_grad(feats, target, params):
     rc = lib().mc_mlp_grad(len(f), _p(f, _u8p), _p(t, _f64p), _p(p, _f64p), ctypes.byref(loss), _p(g, _f64p))
     if rc != MC_OK:
         raise MCError(rc, "mc_mlp_grad failed")
+    return loss.value, g
+
+
+def mlp_grad_noalloc(feats, target, params):
+    """(loss, grad) as mlp_grad, from the library's fixed device workspace
+    (mc_mlp_grad_noalloc: no device allocation; batch <= MC_NOALLOC_MAX_BATCH)."""
+    f = np.ascontiguousarray(feats, np.uint8).reshape(-1, 256)
+    t = np.ascontiguousarray(target, np.float64)
+    p = np.ascontiguousarray(params, np.float64)
+    loss = ctypes.c_double()
+    g = np.zeros(DA_NPARAM)
+    rc = lib().mc_mlp_grad_noalloc(len(f), _p(f, _u8p), _p(t, _f64p), _p(p, _f64p), ctypes.byref(loss),
+                                   _p(g, _f64p))
+    if rc != MC_OK:
+        raise MCError(rc, lib().mc_last_error(None).decode())
     return loss.value, g
 
 
