@@ -47,6 +47,8 @@
 //     accesses only).
 #pragma once
 
+#include <type_traits>
+
 #include "mc_device.hpp"
 
 namespace mcdev {
@@ -1187,9 +1189,22 @@ __device__ __forceinline__ void sweep_chain(SweepShared<T, M, DA>& sh, const Cha
                     if (!DA && gp == g_last && lane == 0 && kTlSlots * (g + 1) <= cd.trace_cap)
                         ((uint64_t*)cd.trace_de)[kTlSlots * g + (wave == 0 ? 14 : 24 + wave)] = wall_clock64();
 #endif
+                    // per-ion diameters: a slice whose partners all have one
+                    // diameter (every slice but those at a species boundary)
+                    // takes the running-minimum contact test of the uniform case
+                    T hj0 = (T)0;
+                    bool slice_uniform = true;
                     if (lane < P) {
                         sh.st_old[wave][lane] = mk4<T>(cur.x, cur.y, cur.z, charge[j]);
-                        if (!UNIFORM_SIGMA) sh.st_half[wave][lane] = half[j];
+                        if (!UNIFORM_SIGMA) {
+                            hj0 = half[j];
+                            sh.st_half[wave][lane] = hj0;
+                        }
+                    }
+                    if constexpr (!UNIFORM_SIGMA && !DA) {
+                        const T hjl = hj0;
+                        hj0 = __shfl(hjl, 0, 64);
+                        slice_uniform = __ballot(lane < P && hjl != hj0) == 0ull;
                     }
                     wave_lds_sync();
                     int bn = bp + 1;
@@ -1207,19 +1222,52 @@ __device__ __forceinline__ void sweep_chain(SweepShared<T, M, DA>& sh, const Cha
                     }
                     T sf = 0;
                     uint32_t nearm = 0;  // delayed acceptance: partners possibly within rc
+                    if constexpr (UNIFORM_SIGMA || DA) {
 #pragma unroll
-                    for (int m = 0; m < P; ++m) {
-                        const T4 p = sh.st_old[wave][m];
-                        const T hj = UNIFORM_SIGMA ? hu : sh.st_half[wave][m];
-                        const T s_ij = hi + hj;
-                        const T d2 = Prec<T>::norm2(p.x - xi, p.y - yi, p.z - zi);
-                        const T d2t = Prec<T>::norm2(p.x - txi, p.y - tyi, p.z - tzi);
-                        sf = Prec<T>::fma(p.w, Prec<T>::rinv(d2t) - Prec<T>::rinv(d2), sf);
-                        if (UNIFORM_SIGMA)
-                            d2t_min = Prec<T>::min(d2t, d2t_min);
+                        for (int m = 0; m < P; ++m) {
+                            const T4 p = sh.st_old[wave][m];
+                            const T hj = UNIFORM_SIGMA ? hu : sh.st_half[wave][m];
+                            const T s_ij = hi + hj;
+                            const T d2 = Prec<T>::norm2(p.x - xi, p.y - yi, p.z - zi);
+                            const T d2t = Prec<T>::norm2(p.x - txi, p.y - tyi, p.z - tzi);
+                            sf = Prec<T>::fma(p.w, Prec<T>::rinv(d2t) - Prec<T>::rinv(d2), sf);
+                            if (UNIFORM_SIGMA)
+                                d2t_min = Prec<T>::min(d2t, d2t_min);
+                            else
+                                ov |= d2t < s_ij * s_ij;
+                            if constexpr (DA) nearm |= (uint32_t)(Prec<T>::min(d2, d2t) < rc2_wide) << m;
+                        }
+                    } else {
+                        // per-ion diameters: the contact test per pair, or as a
+                        // running minimum of the trial distances for a slice
+                        // with one diameter -- exact: min_j d2t_j < s^2 iff some
+                        // d2t_j < s^2, with the one s = hi + hj the per-pair
+                        // test forms for every partner of the slice
+                        auto slice_terms = [&](auto per_pair_c) {
+                            constexpr bool PER_PAIR = decltype(per_pair_c)::value;
+                            T tmin = (T)3.0e38;
+#pragma unroll
+                            for (int m = 0; m < P; ++m) {
+                                const T4 p = sh.st_old[wave][m];
+                                const T d2 = Prec<T>::norm2(p.x - xi, p.y - yi, p.z - zi);
+                                const T d2t = Prec<T>::norm2(p.x - txi, p.y - tyi, p.z - tzi);
+                                sf = Prec<T>::fma(p.w, Prec<T>::rinv(d2t) - Prec<T>::rinv(d2), sf);
+                                if constexpr (PER_PAIR) {
+                                    const T s_ij = hi + sh.st_half[wave][m];
+                                    ov |= d2t < s_ij * s_ij;
+                                } else {
+                                    tmin = Prec<T>::min(d2t, tmin);
+                                }
+                            }
+                            if constexpr (!PER_PAIR) {
+                                const T s_ij = hi + hj0;
+                                ov |= tmin < s_ij * s_ij;
+                            }
+                        };
+                        if (slice_uniform)
+                            slice_terms(std::false_type{});
                         else
-                            ov |= d2t < s_ij * s_ij;
-                        if constexpr (DA) nearm |= (uint32_t)(Prec<T>::min(d2, d2t) < rc2_wide) << m;
+                            slice_terms(std::true_type{});
                     }
                     if constexpr (DA) {
                         // rare: bin the near partners with exact double distances
