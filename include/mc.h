@@ -167,15 +167,21 @@ int mc_sweep(mc_handle* h, int64_t n_sweeps, uint64_t seed);
 int mc_sweep_reduction(mc_handle* h, int64_t n_sweeps, uint64_t seed);
 
 /*
- * Synchronises and returns the running energy (sum of accepted dE since the
- * last re-sum, plus that re-sum) in *e_running, and, if e_exact is not NULL,
- * a fresh double-precision re-sum of the total energy of the current state
- * (which does not reset the running energy).  Energies in kT.
+ * Total energy (Sec. 5.2 records it per cycle; the pair energy
+ * l_B q_i q_j / r_ij of Sec. 5.1 with kT = 1, summed over i < j; no self,
+ * wall or image term).  Synchronises and returns the running energy (sum of
+ * accepted dE since the last re-sum, plus that re-sum) in *e_running, and,
+ * if e_exact is not NULL, a fresh double-precision re-sum of the total
+ * energy of the current state (which does not reset the running energy).
+ * Energies in kT.  Errors: MC_E_ARG for a NULL handle or e_running,
+ * MC_E_STATE after a failed launch, MC_E_DEVICE.
  */
 int mc_energy(mc_handle* h, double* e_running, double* e_exact);
 
 /*
- * Synchronises and returns the pair correlation functions accumulated so far.
+ * Pair correlation functions g_ab(r) (Sec. 5.2, the definition behind Eq.
+ * rho-g-g; ions near the wall are left out as centres).  Synchronises and
+ * returns the functions accumulated so far.
  * Species are the distinct (charge, diameter) pairs, ordered by decreasing
  * charge then increasing diameter.  g [ntypes*ntypes*bins] receives
  * g_ab(r_k) = C_ab(k) / (Ncentre_a * n_b * V_k) (centres: ions with
@@ -219,8 +225,10 @@ int mc_rdf_reset(mc_handle* h);
 /* Number of species and, if the pointers are non-NULL, their charges/diameters. */
 int mc_species(const mc_handle* h, int32_t* ntypes, double* charges, double* diameters);
 
-/* Synchronises and copies the current positions, [n*3] doubles (exact copies
- * of the stored float or double values). */
+/* Synchronises and copies the current positions (the particle array of
+ * Sec. 3.1: x, y, z per ion, in the caller's length unit), [n*3] doubles,
+ * exact copies of the stored float or double values; the caller owns xyz.
+ * MC_E_ARG for a NULL handle or xyz. */
 int mc_get_positions(mc_handle* h, double* xyz);
 
 /*
