@@ -504,3 +504,17 @@ def test_rdf_normalise_is_one_for_independent_ions(oracle):
                 sd = 1.0 / math.sqrt(counts[a, b, k])
                 assert abs(g[a, b, k] - 1.0) < 4.5 * sd + 1e-3, (a, b, k, g[a, b, k], sd)
     assert np.allclose(r, 0.5 * (edges[1:] + edges[:-1]))
+
+
+def test_openmp_build_runs_the_same_chain(oracle):
+    """The oracle's OpenMP build (used only to time the CPU on all host
+    threads) sums each move's partners in another order: the same decisions
+    and energy changes to 1e-12 on a system large enough to split."""
+    from paper_1602_05716_amd import inputs
+    s = inputs.electrolyte(2048, 2048, 1.0, -1.0, 1.0, 1.0, 0.05, 0.7)
+    s.xyz = inputs.random_start(s, 17)
+    a = oracle.Chain(s.xyz, s.q, s.sigma, s.R, s.lB, 2.0, seed=5)
+    b = oracle.Chain(s.xyz, s.q, s.sigma, s.R, s.lB, 2.0, seed=5, threaded=True)
+    ra, rb = a.run(1, trace=s.n), b.run(1, trace=s.n)
+    assert np.array_equal(ra["acc"], rb["acc"])
+    assert np.allclose(ra["dE"], rb["dE"], rtol=1e-12, atol=1e-12)
