@@ -296,12 +296,17 @@ def _gr_sample_run(chain, sweeps, seed, every):
 
 
 def da_leg(args, md):
-    """Surrogate delayed acceptance on the N=32768 system: log moves of a
-    plain run, train the network on the GPU, then run the two-stage chain and
-    the plain chain from the same state for the same number of sweeps."""
+    """Surrogate delayed acceptance on the N=32768 system (or the same
+    electrolyte at --da-n ions): log moves of a plain run, train the network
+    on the GPU, then run the two-stage chain and the plain chain from the
+    same state for the same number of sweeps."""
     import torch
     from paper_1602_05716_amd import analysis, inputs, mc, surrogate
-    system = inputs.large_fp32()
+    if args.da_n == 32768:
+        system = inputs.large_fp32()
+    else:
+        system = inputs.electrolyte(args.da_n // 2, args.da_n - args.da_n // 2, 1.0, -1.0, 1.0, 1.0, 0.05, 0.7)
+        system.xyz = inputs.random_start(system, 0x5EED0002)
     n = system.n
     stream = torch.cuda.Stream()
     sweeps_log = max(1, -(-args.da_log_moves // n))
@@ -321,8 +326,7 @@ def da_leg(args, md):
         coul = lg_chain.train_surrogate(n_log, epochs=1, batch=4096, lr=1e-12, seed=7,
                                         params_in=surrogate.truncated_coulomb_params(4.0))
         x0 = lg_chain.positions()
-    out = {"workload": "1:1 N=32768 phi=0.05 l_B=0.7 (the plain benchmark's system), %d logged moves, "
-                       "network 128-128-128-1 bfloat16" % n_log,
+    out = {"workload": "1:1 N=%d phi=0.05 l_B=0.7, %d logged moves, network 128-128-128-1 bfloat16" % (n, n_log),
            "train_s": t_train, "train_loss": [float(v) for v in tr["loss"]], "val_loss": tr["val_loss"],
            "ref_stage2_reject": tr["ref_stage2_reject"],
            "coulomb_ref_stage2_reject": coul["ref_stage2_reject"], "coulomb_val_loss": coul["val_loss"],
@@ -417,6 +421,7 @@ def main():
     ap.add_argument("--da-log-moves", type=int, default=1000000)
     ap.add_argument("--da-epochs", type=int, default=6)
     ap.add_argument("--da-sweeps", type=int, default=400)
+    ap.add_argument("--da-n", type=int, default=32768, help="ions of the surrogate leg's 1:1 system")
     ap.add_argument("--no-reduction", action="store_true",
                     help="skip the per-move parallel-reduction comparison leg")
     ap.add_argument("--reduction-sweeps", type=int, default=1)
