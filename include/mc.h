@@ -89,9 +89,15 @@ typedef struct mc_options {
                                NULL = a stream owned by the handle                 */
     int32_t band;           /* look-ahead band width in 64-ion groups (0..4),
                                -1 = automatic; affects speed only.  Clamped to
-                               3 for float chains with per-ion diameters and
-                               for the delayed-acceptance kernel               */
-    int32_t waves;          /* waves per workgroup (4 or 8), 0 = automatic         */
+                               3 for float chains with per-ion diameters, for
+                               float chains on eight waves and for the
+                               delayed-acceptance kernel; to 2 for float
+                               chains with both                                */
+    int32_t waves;          /* waves per workgroup (4 or 8), 0 = automatic:
+                               8 for one float chain of at least 4 x 64 ions
+                               per compute unit (N >= 65473 on 256 CUs)
+                               without move logging, else 4.  Delayed
+                               acceptance needs 4                           */
     int32_t workgroups;     /* workgroups serving the chain, 0 = automatic         */
     int64_t trace_moves;    /* record accept bit and dE of the first this many
                                moves of the chain (global move index

@@ -15,6 +15,8 @@ constexpr int kRing = 1024;  // group records kept per chain
 constexpr int kMaxBand = 4;  // largest look-ahead band, in groups
 constexpr int kDaMaxBand = 3;  // ... of chains on the delayed-acceptance kernel
 constexpr int kMaxBandPerIon = 3;  // ... of float chains with per-ion diameters
+constexpr int kMaxBandWide = 3;    // ... of float chains on eight waves per workgroup
+constexpr int kMaxBandWidePerIon = 2;  // ... and per-ion diameters
 
 // Per-group record published by the workgroup that decided the group; one
 // 16-byte transaction, so the tag and the accept mask are read together.

@@ -219,18 +219,25 @@ template <> struct SliceBits<16> { using type = uint16_t; };
 // The newest kChainSlots of them (g-1, g-2[, g-3]) go to the chain step
 // through LDS; the accept masks of the older ones are out before the compute
 // waves finish, and each wave resolves its own slice of their candidates
-// itself.  (The float kernels keep two slots: a third would no longer let
-// two workgroups share a CU's LDS.  The double kernels run one workgroup
+// itself.  (The four-wave float kernels keep two slots: a third would no
+// longer let two workgroups share a CU's LDS.  The double kernels run one workgroup
 // per CU and take three.  The delayed-acceptance kernels, whose LDS also
 // holds the neighbour histograms and the network, take one.)
 template <bool DA> constexpr int kBandSlots = DA ? kDaMaxBand : kMaxBand;
-// ... and of the float kernel for per-ion diameters, whose extra per-partner
-// work leaves no registers for a fourth band group (it would spill, and a
-// spilling persistent kernel runs one workgroup per CU)
-template <typename T, bool UNIFORM_SIGMA, bool DA>
-constexpr int kChainBand = (!DA && !UNIFORM_SIGMA && sizeof(T) == 4) ? kMaxBandPerIon : kBandSlots<DA>;
+// ... and of the float kernels that hold fewer band groups in registers: the
+// one for per-ion diameters, whose extra per-partner work leaves no room for
+// a fourth (it would spill, and a spilling persistent kernel runs one
+// workgroup per CU), and the eight-wave ones, which fit 128 registers so
+// that two workgroups (sixteen waves) share a CU.
+template <typename T, int M, bool UNIFORM_SIGMA, bool DA>
+constexpr int kChainBand = DA ? kBandSlots<DA>
+                              : sizeof(T) != 4 ? kMaxBand
+                              : M == 8 ? (UNIFORM_SIGMA ? kMaxBandWide : kMaxBandWidePerIon)
+                                       : (UNIFORM_SIGMA ? kMaxBand : kMaxBandPerIon);
+// LDS chain slots; the eight-wave float kernels take one, which brings their
+// LDS to 47.8 KB for two workgroups per CU.
 template <typename T, int M, bool DA>
-constexpr int kChainSlots = DA ? 1 : (sizeof(T) == 4 ? 2 : 3);
+constexpr int kChainSlots = DA ? 1 : (sizeof(T) == 4 ? (M == 8 ? 1 : 2) : 3);
 // A compute wave waiting for a partner group more than this many groups
 // before its target polls patiently: the chain publishes about one group
 // every two microseconds, far slower than a tile takes to compute.
@@ -925,7 +932,7 @@ __device__ __forceinline__ void sweep_chain(SweepShared<T, M, DA>& sh, const Cha
     using T4 = typename Prec<T>::T4;
     using IO = PosIO<T>;
     constexpr int P = kGroup / M;
-    constexpr int KB = kChainBand<T, UNIFORM_SIGMA, DA>;
+    constexpr int KB = kChainBand<T, M, UNIFORM_SIGMA, DA>;
     constexpr int LC = SweepShared<T, M, DA>::LC;
     static_assert(KB >= LC, "the chain step's band slots are band groups");
     using SB = typename SliceBits<P>::type;

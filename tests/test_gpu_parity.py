@@ -195,10 +195,26 @@ def test_fp32_large_config_bench_move_size(oracle):
     assert nev > 1000 and ndis <= 2
 
 
+def test_fp32_eight_waves_large_sampled(oracle):
+    """1:1, N = 65536 (phi 0.05, l_B 0.7): at this size the library picks
+    eight waves per workgroup (two workgroups, sixteen waves per CU, band 3,
+    one LDS chain slot); one sweep at the benchmark's move size, every 97th
+    move checked against the exact double dE."""
+    from paper_1602_05716_amd import inputs, mc
+    sy = inputs.electrolyte(32768, 32768, 1.0, -1.0, 1.0, 1.0, 0.05, 0.7)
+    sy.xyz = inputs.random_start(sy, 0x5EED0006)
+    with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision="fp32") as ch:
+        st = ch.stats()
+    assert st["waves"] == 8 and st["band"] == 3, st
+    err, ndis, nev = _fp32_check(oracle, sy, 1, 0x5EED0006, 10.4, sample_every=97)
+    assert nev > 500 and ndis <= 2
+
+
 def test_fp32_2to1_full_size_sampled(oracle):
     """2:1, N = 98304 (32768 at +2 with sigma 1.0, 65536 at -1 with sigma
     0.8), phi = 0.1, l_B = 0.7: per-ion diameters, three targets per
-    workgroup and sweep; one sweep, every 97th move checked against the
+    workgroup and sweep, eight waves per workgroup and band 2 (the library's
+    choice at this size); one sweep, every 97th move checked against the
     exact double dE."""
     from paper_1602_05716_amd import inputs
     sy = inputs.asymmetric_2to1()
