@@ -38,7 +38,7 @@
 //     the pending band groups' masks (all rejected), while wave 1 sums the
 //     older pending groups' masked rows as their masks arrive.  Each true
 //     correction then costs one evaluation when the guess was right, a few
-//     more iterations when not.
+//     more iterations (updating the row sum by the flipped bits) when not.
 //   * Publication: the accept mask goes out at once in the group record; the
 //     new positions are written in place, double buffered by sweep parity,
 //     each 16-byte record carrying the sweep index of the trial that produced
@@ -347,6 +347,33 @@ __device__ __forceinline__ T masked_row_sum(const T* __restrict__ row, T* fac, u
     return (a[0] + a[1]) + (a[2] + a[3]);
 }
 
+// The row sum of mask `to` from that of mask `from` (at most kFewFlips bits
+// apart): for every bit that differs, in ascending order (a fixed order:
+// deterministic), adds the entry if the bit is set in `to` and subtracts it
+// otherwise.  Cheaper than a full masked_row_sum for a few flips: a scalar
+// bit scan and one LDS read per flip, the reads issued before the first add.
+constexpr int kFewFlips = 4;
+template <typename T>
+__device__ __forceinline__ T row_sum_update(const T* __restrict__ row, T own, uint64_t from, uint64_t to) {
+    uint64_t f = from ^ to;
+    T v[kFewFlips];
+    bool up[kFewFlips];
+#pragma unroll
+    for (int q = 0; q < kFewFlips; ++q) {
+        v[q] = 0;
+        up[q] = true;
+        if (f) {
+            const int j = __builtin_ctzll(f);
+            f &= f - 1;
+            v[q] = row[j];
+            up[q] = ((to >> j) & 1ull) != 0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kFewFlips; ++q) own = up[q] ? own + v[q] : own - v[q];
+    return own;
+}
+
 // Publishes group g: its accept mask in the group record, then the new
 // positions (trial position if accepted, old one otherwise), each tagged with
 // the sweep index.
@@ -573,13 +600,17 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
         dec = canx && !ovown && (dE <= shift || dE < thr_eff);
         return __ballot(dec);
     };
-    // iterates from mask a (row sum own) to the fixed point
+    // iterates from mask a (row sum own) to the fixed point; a step that
+    // flips few bits updates the row sum by them instead of summing the row
     auto solve = [&](double Sx, bool canx, uint64_t a, T own) {
         uint64_t na = rule(Sx, canx, a, own);
         ++it;
         while (na != a && it <= kGroup + 2) {
+            if (__popcll(na ^ a) <= kFewFlips)
+                own = row_sum_update<T>(sh.c_own[lane], own, a, na);
+            else
+                own = masked_row_sum<T>(sh.c_own[lane], sh.fac, na);
             a = na;
-            own = masked_row_sum<T>(sh.c_own[lane], sh.fac, a);
             na = rule(Sx, canx, a, own);
             ++it;
         }
@@ -597,16 +628,18 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
         corr = sh.h_corr[lane];
         ovb |= ((sh.h_ov >> lane) & 1ull) != 0;
     };
+    // group g-1's correction, added to corr once its mask arrives
+    auto g1_part = [&]() {
+        const GroupRec r = wait_rec(rec_r, g - 1, ctl);
+#ifdef MC_TIMELINE
+        tl2 = wall_clock64();
+#endif
+        corr += (double)masked_row_sum<T>(sh.c_b[0][lane], sh.fac, r.acc);
+        ovb |= ((r.acc & ovtb[0]) | (~r.acc & ovob[0])) != 0;
+    };
     if (early) {
         if (LC > 1 && band >= 2) helper_part();
-        if (band >= 1) {
-            const GroupRec r = wait_rec(rec_r, g - 1, ctl);
-#ifdef MC_TIMELINE
-            tl2 = wall_clock64();
-#endif
-            corr += (double)masked_row_sum<T>(sh.c_b[0][lane], sh.fac, r.acc);
-            ovb |= ((r.acc & ovtb[0]) | (~r.acc & ovob[0])) != 0;
-        }
+        if (band >= 1) g1_part();
         // exact energy change of the (already decided) trials
         const T own = acc ? masked_row_sum<T>(sh.c_own[lane], sh.fac, acc) : (T)0;
         dE = lq * ((St + corr) + (double)own);
@@ -638,12 +671,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
 #ifdef MC_TIMELINE
             tl6 = wall_clock64();
 #endif
-            const GroupRec r = wait_rec(rec_r, g - 1, ctl);
-#ifdef MC_TIMELINE
-            tl2 = wall_clock64();
-#endif
-            corr += (double)masked_row_sum<T>(sh.c_b[0][lane], sh.fac, r.acc);
-            ovb |= ((r.acc & ovtb[0]) | (~r.acc & ovob[0])) != 0;
+            g1_part();
 #ifdef MC_TIMELINE
             tl4 = wall_clock64();
 #endif
