@@ -486,6 +486,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
 #ifdef MC_TIMELINE
     // diagnostic build only: per-group wall-clock stamps in the dE trace buffer
     uint64_t tl0 = wall_clock64(), tl1 = 0, tl2 = 0, tl3 = 0, tl4 = 0, tl5 = 0, tl6 = 0, tlA = 0, tlB = 0, tlC = 0;
+    uint64_t tlE = 0, tlR = 0, tlN = 0, tlN1 = 0;  // early check done, first row sum done, row sums (in the first solve)
 #endif
     // the waves' partial sums
     wait_lds_at_least(&sh.ready, M, ctl);
@@ -586,7 +587,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
         }
     }
 #ifdef MC_TIMELINE
-    tlB = wall_clock64();
+    tlB = tlE = wall_clock64();
 #endif
     // One evaluation of the sequential rule inside the group given an accept
     // mask `a` of the own group (row sum `own`): the decisions every lane
@@ -610,6 +611,9 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
                 own = row_sum_update<T>(sh.c_own[lane], own, a, na);
             else
                 own = masked_row_sum<T>(sh.c_own[lane], sh.fac, na);
+#ifdef MC_TIMELINE
+            if (tlN++ == 0) tlR = wall_clock64();
+#endif
             a = na;
             na = rule(Sx, canx, a, own);
             ++it;
@@ -658,6 +662,7 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
         if (LC > 1 && band >= 2) {
 #ifdef MC_TIMELINE
             tlC = wall_clock64();  // end of the first solve
+            tlN1 = tlN;
 #endif
             helper_part();
 #ifdef MC_TIMELINE
@@ -713,6 +718,9 @@ __device__ __forceinline__ void chain_step(SweepShared<T, M, DA>& sh, const Chai
             tl[8] = tlA;
             tl[9] = tlB;
             tl[10] = tlC;
+            tl[29] = tlE;
+            tl[30] = tlR;
+            tl[31] = tlN1;
         }
     }
 #endif
