@@ -254,6 +254,23 @@ def asymmetric_leg(args, rsq_peak):
             "rdf_samples": r["samples"], "g_pairs": int(r["g"].shape[0] * r["g"].shape[1])}
 
 
+def large_n_leg(args, rsq_peak):
+    """The same 1:1 electrolyte at N = 131072, where the launch is bound by
+    the pair terms rather than by the decision chain (the library picks
+    eight waves per workgroup there): move size tuned to about 40 %
+    acceptance, about 2e11 pair terms timed with HIP events."""
+    from paper_1602_05716_amd import compare
+    r = compare.measure(args.large_n, reduction_sweeps=0)
+    sk = r["sweep_kernel"]
+    n = r["n"]
+    rate = n * (n - 1.0) / (sk["event_ms_per_sweep"] * 1e-3)
+    return {"workload": "1:1 N=%d phi=0.05 l_B=0.7, seeded random start, move size tuned to ~40%% acceptance" % n,
+            "kernel": "sweep_kernel<float,%d>" % r["waves"], "band": r["band"], "sweeps": sk["sweeps"],
+            "max_disp": r["max_disp"], "acceptance": sk["acceptance"], "ms_per_sweep": sk["ms_per_sweep"],
+            "event_ms_per_sweep": sk["event_ms_per_sweep"], "kernel_pair_terms_per_s": rate,
+            "rsq_frac": 2.0 * rate / rsq_peak}
+
+
 def reduction_leg(chain, args, sweep_rate):
     """The paper's GPU comparison code (Sec. 4): the same chain continued by
     the per-move parallel-reduction scheme, one launch per trial move, after
@@ -415,12 +432,14 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-asym", action="store_true", help="skip the 2:1 N=98304 leg")
     ap.add_argument("--asym-sweeps", type=int, default=40)
+    ap.add_argument("--large-n", type=int, default=131072,
+                    help="ions of the pair-term-bound 1:1 leg (0: skip it)")
     ap.add_argument("--batch-sweeps", type=int, default=1000)
     ap.add_argument("--seq-sweeps", type=int, default=20)
     ap.add_argument("--no-da", action="store_true", help="skip the surrogate delayed-acceptance leg")
     ap.add_argument("--da-log-moves", type=int, default=1000000)
     ap.add_argument("--da-epochs", type=int, default=6)
-    ap.add_argument("--da-sweeps", type=int, default=400)
+    ap.add_argument("--da-sweeps", type=int, default=1500)
     ap.add_argument("--da-n", type=int, default=32768, help="ions of the surrogate leg's 1:1 system")
     ap.add_argument("--no-reduction", action="store_true",
                     help="skip the per-move parallel-reduction comparison leg")
@@ -515,6 +534,11 @@ def main():
         log("2:1 N=98304 leg (%d sweeps)" % args.asym_sweeps)
         asym = asymmetric_leg(args, rsq_peak)
 
+    large = None
+    if args.large_n > 0:
+        log("1:1 N=%d leg" % args.large_n)
+        large = large_n_leg(args, rsq_peak)
+
     batched = None
     if not args.no_batched:
         log("batched ensemble leg")
@@ -553,6 +577,7 @@ def main():
                       "plain_same_run_as_da": da["plain"]["ess_per_s"] if da else None},
         "batched": batched,
         "asymmetric_2to1": asym,
+        "large_n": large,
         "surrogate_da": da,
         "reduction_scheme": reduction,
         "energy": {"tau_int_sweeps": tau, "e_running": e_run, "e_resum": e_exact,
