@@ -37,26 +37,40 @@ def _log(*a):
 
 
 def run(n: int, sweeps: int, equil: int, every: int, rmax: float, bins: int, seed: int, chunk: int = 100,
-        margin: float | None = None, debye_A: float = inputs.PAPER_DEBYE_A, trace: bool = False):
+        margin: float | None = None, debye_A: float = inputs.PAPER_DEBYE_A, trace: bool = False,
+        save: str = "", resume: str = ""):
+    """With `resume`, the chain continues from a checkpoint written by an
+    earlier run's `save` (same system, seed and sampling options): no
+    equilibration, and the g(r) counts go on accumulating from the saved ones."""
     from . import mc
     t0 = time.perf_counter()
-    sy = inputs.three_to_one(n, seed, debye_A)
-    _log("start built: N=%d R=%.2f (%.1f s)" % (n, sy.R, time.perf_counter() - t0))
+    sy = inputs.three_to_one(n, seed, debye_A, start=not resume)
+    _log("system built: N=%d R=%.2f (%.1f s)" % (n, sy.R, time.perf_counter() - t0))
     md = sy.R / 3.0  # cube side 2 md = L / 3
     if margin is None:  # every neighbour counted at least ten bare Debye lengths inside the wall
         margin = 10.0 * sy.meta["kappa_inv"]
     # the handle's own stream: nothing here needs another GPU runtime
-    with mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision="fp32", max_disp=md, resum_every=100,
-                  rdf_every=every, rdf_bins=bins, rdf_rmax=rmax, rdf_margin=margin,
-                  trace_moves=(equil + sweeps) * n if trace else 0) as ch:
-        done = 0
-        while done < equil:
-            k = min(chunk, equil - done)
-            ch.sweep(k, seed)
-            ch.energy()
-            done += k
-            _log("equilibration %d / %d sweeps" % (done, equil))
-        ch.rdf_reset()
+    if resume:
+        chain = mc.Chain.load(resume)
+        o = chain.opt
+        if (chain.n != n or o.rdf_every != every or o.rdf_bins != bins or o.rdf_rmax != rmax
+                or abs(o.rdf_margin - margin) > 1e-12 * max(1.0, margin)):
+            chain.close()
+            raise ValueError("the checkpoint was written for another system or g(r) sampling")
+    else:
+        chain = mc.Chain(sy.xyz, sy.q, sy.sigma, sy.R, sy.lB, precision="fp32", max_disp=md, resum_every=100,
+                         rdf_every=every, rdf_bins=bins, rdf_rmax=rmax, rdf_margin=margin,
+                         trace_moves=(equil + sweeps) * n if trace else 0)
+    with chain as ch:
+        if not resume:
+            done = 0
+            while done < equil:
+                k = min(chunk, equil - done)
+                ch.sweep(k, seed)
+                ch.energy()
+                done += k
+                _log("equilibration %d / %d sweeps" % (done, equil))
+            ch.rdf_reset()
         s0 = ch.stats()["sweeps"]
         t1 = time.perf_counter()
         done = 0
@@ -73,6 +87,9 @@ def run(n: int, sweeps: int, equil: int, every: int, rmax: float, bins: int, see
         e_run, e_ex = ch.energy(exact=True)
         if trace:
             st["trace"] = ch.trace((equil + sweeps) * n)
+        if save:
+            ch.save(save)
+            _log("checkpoint written: %s (sweep %d)" % (save, st["sweeps"]))
     types, keys = sy.types()
     n_of_type = np.bincount(types, minlength=len(keys))
     return sy, md, r, st, es, wall, n_of_type, (e_run, e_ex), margin
@@ -130,6 +147,9 @@ def main():
     ap.add_argument("--fit", type=float, nargs=2, default=[0.0, 0.0],
                     help="far-field window in diameters (0 0: 4.2 to 7.9 bare Debye lengths)")
     ap.add_argument("--out", default="")
+    ap.add_argument("--save", default="", help="write a checkpoint of the chain at the end")
+    ap.add_argument("--resume", default="",
+                    help="continue the chain of this checkpoint (same system and sampling options)")
     ap.add_argument("--pool", nargs="+", default=None,
                     help="analysis only (no GPU): pool the counts of these saved runs of one system")
     a = ap.parse_args()
@@ -142,7 +162,8 @@ def main():
         print(json.dumps(pooled(a.pool, tuple(a.fit))), flush=True)
         return
     sy, md, r, st, es, wall, n_of_type, (e_run, e_ex), margin = run(a.n, a.sweeps, a.equil, a.every, a.rmax, a.bins, a.seed,
-                                                             a.chunk, debye_A=a.debye_A)
+                                                             a.chunk, debye_A=a.debye_A, save=a.save,
+                                                             resume=a.resume)
     dr = a.rmax / a.bins
     r_c = (np.arange(a.bins) + 0.5) * dr
     if a.out:
@@ -151,7 +172,8 @@ def main():
                  margin=margin, debye_A=a.debye_A)
     tau = analysis.integrated_time(es) if len(es) > 8 else float("nan")
     out = {"n": a.n, "debye_A": a.debye_A, "R": sy.R, "max_disp": md, "rdf_margin": margin, "rmax": a.rmax,
-           "sweeps": a.sweeps, "equil": a.equil, "every": a.every,
+           "sweeps": a.sweeps, "equil": 0 if a.resume else a.equil, "every": a.every,
+           "resumed_at_sweep": (st["sweeps"] - a.sweeps) if a.resume else None, "total_sweeps": st["sweeps"],
            "samples": r["samples"], "wall_s": wall, "ms_per_sweep": 1e3 * wall / max(1, a.sweeps),
            "acceptance": st["accepted"] / max(1, st["moves"]), "tau_int_sweeps": tau,
            "paper_tau_int": PAPER_TAU_INT, "e_running": e_run, "e_resum": e_ex,

@@ -204,17 +204,20 @@ def three_to_one_density(debye_A: float = PAPER_DEBYE_A) -> tuple[float, float]:
     return n_plus, 3.0 * n_plus
 
 
-def three_to_one(n: int = 1 << 20, seed: int = 0x5EED0007, debye_A: float = PAPER_DEBYE_A) -> System:
+def three_to_one(n: int = 1 << 20, seed: int = 0x5EED0007, debye_A: float = PAPER_DEBYE_A,
+                 start: bool = True) -> System:
     """The paper's 3:-1 system with n ions (n / 4 at +3, 3 n / 4 at -1, all
     of diameter 1 = 7.5 A), at the density of bare Debye length debye_A
     (the paper's 28.53 A: phi = (n_+ + n_-) pi / 6, about 1.0e-3), in a
-    hard-wall sphere; uniform random start without overlap."""
+    hard-wall sphere; uniform random start without overlap (none with
+    start=False, for a chain resumed from a checkpoint)."""
     if n % 4:
         raise ValueError("n must be a multiple of 4")
     n_plus, n_minus = three_to_one_density(debye_A)
     phi = (n_plus + n_minus) * np.pi / 6.0
     s = electrolyte(n // 4, 3 * n // 4, 3.0, -1.0, 1.0, 1.0, phi, PAPER_BJERRUM_A / PAPER_DIAMETER_A,
                     name=f"3:-1 N={n}, bare Debye length {debye_A} A (diameter 7.5 A)")
-    s.xyz = random_start(s, seed)
+    if start:
+        s.xyz = random_start(s, seed)
     s.meta.update(seed=seed, kappa_inv=debye_A / PAPER_DIAMETER_A, phi=phi, debye_A=debye_A)
     return s
