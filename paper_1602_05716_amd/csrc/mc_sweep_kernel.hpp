@@ -238,6 +238,17 @@ constexpr int kChainBand = DA ? kBandSlots<DA>
 // LDS to 47.8 KB for two workgroups per CU.
 template <typename T, int M, bool DA>
 constexpr int kChainSlots = DA ? 1 : (sizeof(T) == 4 ? (M == 8 ? 1 : 2) : 3);
+// Partners per wave in a tile of a decided partner group.  The eight-wave
+// float kernels take 64: wave w takes every eighth decided group (w, w + 8,
+// ... after the oldest) whole, so that a tile's fixed costs (its load and
+// version check, the LDS staging and its waits, the double accumulation) fall
+// on 64 pair terms a lane instead of 8, and every lane loads.  Measured 12-14 %
+// faster where the pair terms bound (N >= 65536); with four waves, 32-partner
+// slices were slower (the last decided tile lengthens the hand-off that the
+// decision chain waits for).  The other kernels split every group over all
+// their waves.
+template <typename T, int M, bool DA>
+constexpr int kDecidedSlice = (sizeof(T) == 4 && M == 8 && !DA) ? 64 : kGroup / M;
 // A compute wave waiting for a partner group more than this many groups
 // before its target polls patiently: the chain publishes about one group
 // every two microseconds, far slower than a tile takes to compute.
@@ -247,10 +258,12 @@ template <typename T, int M, bool DA = false>
 struct SweepShared {
     using T4 = typename Prec<T>::T4;
     static constexpr int P = kGroup / M;
+    static constexpr int PD = kDecidedSlice<T, M, DA>;
     static constexpr int KB = kBandSlots<DA>;
     static constexpr int LC = kChainSlots<T, M, DA>;
     using SB = typename SliceBits<P>::type;
     // per compute wave: staging of the current partner slice {x, y, z, q}
+    // (a decided tile of PD > P partners continues in st_old2 / st_half2)
     T4 st_old[M][P];
     T4 st_new[M][P];
     T st_half[M][P];
@@ -298,6 +311,9 @@ struct SweepShared {
     // the space of c_own and c_b (free between the chain wave's release and
     // the next hand-off)
     __device__ uint16_t* h1() { return reinterpret_cast<uint16_t*>(&c_own[0][0]); }
+    // placed last, so that the fields above keep their offsets
+    T4 st_old2[M][PD > P ? PD - P : 1];
+    T st_half2[M][PD > P ? PD - P : 1];
 };
 
 // The 64-bit word of overlap bits that the waves' slices tile.
@@ -988,9 +1004,11 @@ __device__ __forceinline__ void sweep_chain(SweepShared<T, M, DA>& sh, const Cha
     const int64_t g_end = g_begin + (int64_t)n_sweeps * nb;
 
     if (threadIdx.x == 0) {
-        sh.ready = 0;
-        sh.consumed = 0;
-        sh.h_done = 0;
+        // one store each (a merged 64-bit store of zeros has kept a register
+        // pair live through the whole kernel)
+        __hip_atomic_store(&sh.ready, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(&sh.consumed, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(&sh.h_done, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (k_wg == 0) cd.clk[0] = wall_clock64();
     }
     if constexpr (DA) {
@@ -1207,11 +1225,22 @@ __device__ __forceinline__ void sweep_chain(SweepShared<T, M, DA>& sh, const Cha
             // ---- decided partner groups g-nb+1 .. g-band-1, in stream order.  The next
             // tile is loaded speculatively while this one is computed (float path); a
             // record whose version is not the expected one yet is loaded again.
+            // With KD > 1 decided groups to a tile round, M / KD waves share
+            // each group, PD partners a wave.
             {
+                constexpr int PD = kDecidedSlice<T, M, DA>;
+                constexpr int KD = PD / P;
+                static_assert(KD * P == PD && M % KD == 0 && (!DA || KD == 1), "decided tiles");
                 const int64_t g_last = g - band - 1;
                 int64_t sp = (b + 1 < nb) ? s - 1 : s;   // sweep and group of g-nb+1
                 int bp = (b + 1 < nb) ? b + 1 : 0;
-                const int jl = wave * P + (lane < P ? lane : 0);
+                const int dphase = wave / (M / KD);      // this wave's first group: g-nb+1+dphase
+                for (int k = 0; k < dphase; ++k)
+                    if (++bp == nb) {
+                        bp = 0;
+                        ++sp;
+                    }
+                const int jl = (wave % (M / KD)) * PD + (lane < PD ? lane : 0);
                 typename IO::Rec nxt{};
                 bool have_next = false;
                 // uniform diameters: overlap with any of these partners iff the
@@ -1220,16 +1249,16 @@ __device__ __forceinline__ void sweep_chain(SweepShared<T, M, DA>& sh, const Cha
                 // a working-precision squared distance below this bound may be
                 // below rc^2 exactly (the bound is a relative 1e-5 above it)
                 const T rc2_wide = (T)(cd.da_rc * cd.da_rc * (1.0 + 1e-5));
-                for (int64_t gp = g - nb + 1; gp <= g_last; ++gp) {
+                for (int64_t gp = g - nb + 1 + dphase; gp <= g_last; gp += KD) {
                     const int j = bp * kGroup + jl;
                     typename IO::Rec cur;
-                    if (have_next && __ballot(lane < P && nxt.ver != (uint32_t)sp) == 0ull)
+                    if (have_next && __ballot(lane < PD && nxt.ver != (uint32_t)sp) == 0ull)
                         cur = nxt;
                     else
-                        cur = IO::load_valid(pos_r, (uint32_t)((sp & 1) * npad + j), (uint32_t)sp, lane < P, ctl,
+                        cur = IO::load_valid(pos_r, (uint32_t)((sp & 1) * npad + j), (uint32_t)sp, lane < PD, ctl,
                                              g - gp > kPatientDistance);
 #ifdef MC_TIMELINE
-                    if (!DA && gp == g_last && lane == 0 && kTlSlots * (g + 1) <= cd.trace_cap)
+                    if (!DA && gp + KD > g_last && lane == 0 && kTlSlots * (g + 1) <= cd.trace_cap)
                         ((uint64_t*)cd.trace_de)[kTlSlots * g + (wave == 0 ? 14 : 24 + wave)] = wall_clock64();
 #endif
                     // per-ion diameters: a slice whose partners all have one
@@ -1237,39 +1266,48 @@ __device__ __forceinline__ void sweep_chain(SweepShared<T, M, DA>& sh, const Cha
                     // takes the running-minimum contact test of the uniform case
                     T hj0 = (T)0;
                     bool slice_uniform = true;
-                    if (lane < P) {
-                        sh.st_old[wave][lane] = mk4<T>(cur.x, cur.y, cur.z, charge[j]);
+                    if (lane < PD) {
+                        const bool lo = PD == P || lane < P;
+                        const int ls = lo ? lane : lane - P;
+                        (lo ? sh.st_old[wave] : sh.st_old2[wave])[ls] = mk4<T>(cur.x, cur.y, cur.z, charge[j]);
                         if (!UNIFORM_SIGMA) {
                             hj0 = half[j];
-                            sh.st_half[wave][lane] = hj0;
+                            (lo ? sh.st_half[wave] : sh.st_half2[wave])[ls] = hj0;
                         }
                     }
                     if constexpr (!UNIFORM_SIGMA && !DA) {
                         const T hjl = hj0;
                         hj0 = __shfl(hjl, 0, 64);
-                        slice_uniform = __ballot(lane < P && hjl != hj0) == 0ull;
+                        slice_uniform = __ballot(lane < PD && hjl != hj0) == 0ull;
                     }
                     wave_lds_sync();
-                    int bn = bp + 1;
+                    int bn = bp;
                     int64_t sn = sp;
-                    if (bn == nb) {
-                        bn = 0;
-                        ++sn;
-                    }
+                    for (int k = 0; k < KD; ++k)
+                        if (++bn == nb) {
+                            bn = 0;
+                            ++sn;
+                        }
                     have_next = false;
                     if constexpr (sizeof(T) == 4) {
-                        if (gp + 1 <= g_last) {
-                            if (lane < P) nxt = IO::load(pos_r, (uint32_t)((sn & 1) * npad + bn * kGroup + jl));
+                        if (gp + KD <= g_last) {
+                            if (lane < PD) nxt = IO::load(pos_r, (uint32_t)((sn & 1) * npad + bn * kGroup + jl));
                             have_next = true;
                         }
                     }
                     T sf = 0;
                     uint32_t nearm = 0;  // delayed acceptance: partners possibly within rc
                     if constexpr (UNIFORM_SIGMA || DA) {
+                        // a P-partner piece at a time (a loop, not unrolled:
+                        // the registers of the four-wave kernels' slices)
+#pragma nounroll
+                        for (int c = 0; c < KD; ++c)
 #pragma unroll
-                        for (int m = 0; m < P; ++m) {
-                            const T4 p = sh.st_old[wave][m];
-                            const T hj = UNIFORM_SIGMA ? hu : sh.st_half[wave][m];
+                        for (int mm = 0; mm < P; ++mm) {
+                            const int m = c * P + mm;
+                            const T4 p = c == 0 ? sh.st_old[wave][mm] : sh.st_old2[wave][(c - 1) * P + mm];
+                            const T hj = UNIFORM_SIGMA ? hu
+                                         : c == 0 ? sh.st_half[wave][mm] : sh.st_half2[wave][(c - 1) * P + mm];
                             const T s_ij = hi + hj;
                             const T d2 = Prec<T>::norm2(p.x - xi, p.y - yi, p.z - zi);
                             const T d2t = Prec<T>::norm2(p.x - txi, p.y - tyi, p.z - tzi);
@@ -1289,14 +1327,17 @@ __device__ __forceinline__ void sweep_chain(SweepShared<T, M, DA>& sh, const Cha
                         auto slice_terms = [&](auto per_pair_c) {
                             constexpr bool PER_PAIR = decltype(per_pair_c)::value;
                             T tmin = (T)3.0e38;
+#pragma nounroll
+                            for (int c = 0; c < KD; ++c)
 #pragma unroll
-                            for (int m = 0; m < P; ++m) {
-                                const T4 p = sh.st_old[wave][m];
+                            for (int mm = 0; mm < P; ++mm) {
+                                const T4 p = c == 0 ? sh.st_old[wave][mm] : sh.st_old2[wave][(c - 1) * P + mm];
                                 const T d2 = Prec<T>::norm2(p.x - xi, p.y - yi, p.z - zi);
                                 const T d2t = Prec<T>::norm2(p.x - txi, p.y - tyi, p.z - tzi);
                                 sf = Prec<T>::fma(p.w, Prec<T>::rinv(d2t) - Prec<T>::rinv(d2), sf);
                                 if constexpr (PER_PAIR) {
-                                    const T s_ij = hi + sh.st_half[wave][m];
+                                    const T s_ij = hi + (c == 0 ? sh.st_half[wave][mm]
+                                                                : sh.st_half2[wave][(c - 1) * P + mm]);
                                     ov |= d2t < s_ij * s_ij;
                                 } else {
                                     tmin = Prec<T>::min(d2t, tmin);
