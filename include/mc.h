@@ -94,8 +94,8 @@ typedef struct mc_options {
                                delayed-acceptance kernel; to 2 for float
                                chains with both                                */
     int32_t waves;          /* waves per workgroup (4 or 8), 0 = automatic:
-                               8 for one float chain of at least 4 x 64 ions
-                               per compute unit (N >= 65473 on 256 CUs)
+                               8 for one float chain of at least 3 x 64 ions
+                               per compute unit (N >= 49089 on 256 CUs)
                                without move logging, else 4.  Delayed
                                acceptance needs 4                           */
     int32_t workgroups;     /* workgroups serving the chain, 0 = automatic         */

@@ -846,14 +846,13 @@ int create_handle(int32_t n_chains, const mc_chain_spec* specs, const mc_options
         setup_chain(h->chains[k], specs[k], opt);
         h->uniform_sigma = h->uniform_sigma && h->chains[k].uniform_sigma;
     }
-    // Automatic waves per workgroup: eight for one float chain whose groups
-    // outnumber the four-wave workgroups twice over (each workgroup then
-    // serves two targets or more a sweep, and the launch is bound by the
-    // pair terms rather than by the decision chain: sixteen waves per CU
-    // hide more latency than eight), four otherwise and when moves are logged
-    // (the delayed-acceptance kernels have four waves).
+    // Automatic waves per workgroup: eight for one float chain of at least
+    // three groups per CU (measured: from there on the launch is bound by the
+    // pair terms rather than by the decision chain, and sixteen waves per CU,
+    // each taking whole decided groups, are the faster), four otherwise and
+    // when moves are logged (the delayed-acceptance kernels have four waves).
     if (opt.waves == 0 && !h->fp64 && n_chains == 1 && opt.log_moves == 0 &&
-        h->chains[0].nb >= 4 * h->dev.cus)
+        h->chains[0].nb >= 3 * h->dev.cus)
         h->waves = 8;
     // the float kernels for per-ion diameters and with eight waves hold
     // fewer band groups
