@@ -176,6 +176,19 @@ def test_fp32_asymmetric_parity(oracle):
     assert ndis <= 2
 
 
+@pytest.mark.parametrize("n,band", [(65, 0), (200, 1), (777, 3), (1000, 0), (1500, 3)])
+def test_fp32_eight_waves_ragged(oracle, n, band):
+    """Float, eight waves, uniform diameters: each wave takes every eighth
+    decided partner group whole, so with few groups some waves have none and
+    the others one or two; ragged N (padding lanes)."""
+    sy = _sys(n // 2, n - n // 2, seed=300 + n)
+    if n % 2:
+        sy.q = sy.q.copy()
+        sy.q[-1] = 0.0  # keep neutral with an odd count
+    err, ndis, nev = _fp32_check(oracle, sy, 3, 0xE1 + n, 1.2, band=band, waves=8)
+    assert ndis <= 2
+
+
 def test_fp32_large_config_sampled(oracle):
     """1:1, N = 32768, phi = 0.05, l_B = 0.7 in the benchmark's launch shape:
     two sweeps, every 31st move checked against the exact double dE."""
