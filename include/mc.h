@@ -94,10 +94,10 @@ typedef struct mc_options {
                                delayed-acceptance kernel; to 2 for float
                                chains with both                                */
     int32_t waves;          /* waves per workgroup (4 or 8), 0 = automatic:
-                               8 for one float chain of at least 3 x 64 ions
-                               per compute unit (N >= 49089 on 256 CUs)
-                               without move logging, else 4.  Delayed
-                               acceptance needs 4                           */
+                               8 for float chains of at least 3 groups of 64
+                               per compute unit in all (one chain: N >= 49089
+                               on 256 CUs) without move logging, else 4.
+                               Delayed acceptance needs 4                   */
     int32_t workgroups;     /* workgroups serving the chain, 0 = automatic         */
     int64_t trace_moves;    /* record accept bit and dE of the first this many
                                moves of the chain (global move index

@@ -846,13 +846,16 @@ int create_handle(int32_t n_chains, const mc_chain_spec* specs, const mc_options
         setup_chain(h->chains[k], specs[k], opt);
         h->uniform_sigma = h->uniform_sigma && h->chains[k].uniform_sigma;
     }
-    // Automatic waves per workgroup: eight for one float chain of at least
-    // three groups per CU (measured: from there on the launch is bound by the
-    // pair terms rather than by the decision chain, and sixteen waves per CU,
-    // each taking whole decided groups, are the faster), four otherwise and
-    // when moves are logged (the delayed-acceptance kernels have four waves).
-    if (opt.waves == 0 && !h->fp64 && n_chains == 1 && opt.log_moves == 0 &&
-        h->chains[0].nb >= 3 * h->dev.cus)
+    // Automatic waves per workgroup: eight for float chains of at least three
+    // groups per CU in all (measured, for one chain and for the 256-chain
+    // ensemble: from there on the workgroups serve several targets a sweep,
+    // the launch is bound by the pair terms rather than by the decision
+    // chain, and sixteen waves per CU, each taking whole decided groups, are
+    // the faster), four otherwise and when moves are logged (the
+    // delayed-acceptance kernels have four waves).
+    int64_t groups = 0;
+    for (const Chain& c : h->chains) groups += c.nb;
+    if (opt.waves == 0 && !h->fp64 && opt.log_moves == 0 && groups >= 3 * h->dev.cus)
         h->waves = 8;
     // the float kernels for per-ion diameters and with eight waves hold
     // fewer band groups
