@@ -185,7 +185,9 @@ def test_ensemble_sampled_chains_fp32(oracle):
     """The batched-ensemble workload (256 chains, N log-uniform in [500, 8000],
     phi in [0.005, 0.1], l_B in [0.5, 2]) in one launch with the autotuned
     schedule; 8 chains stratified by N are checked move by move (every 7th
-    move of two sweeps) against the exact double dE of the same float state."""
+    move of two sweeps) against the exact double dE of the same float state.
+    The launch runs on eight waves per workgroup, the library's choice for
+    this many groups."""
     from paper_1602_05716_amd import inputs, mc
     params = inputs.ensemble_params(256)
     systems = [inputs.ensemble_chain(*p) for p in params]
@@ -197,6 +199,8 @@ def test_ensemble_sampled_chains_fp32(oracle):
     # the trace covers the calibration sweep and the checked sweeps
     with mc.Batch(systems, precision="fp32", max_disp=[0.5] * 256,
                   trace_moves=max(s.n for s in systems) * (1 + sweeps), resum_every=0) as b:
+        # 11014 groups in all: the eight-wave kernel, whole decided groups per wave
+        assert b.stats(0)["waves"] == 8
         a, bb = b.autotune(1, seed)
         _say("autotune model a=%.3f b=%.3f us" % (a, bb))
         w, _ = b.schedule()
