@@ -1225,8 +1225,10 @@ __device__ __forceinline__ void sweep_chain(SweepShared<T, M, DA>& sh, const Cha
             // ---- decided partner groups g-nb+1 .. g-band-1, in stream order.  The next
             // tile is loaded speculatively while this one is computed (float path); a
             // record whose version is not the expected one yet is loaded again.
-            // With KD > 1 decided groups to a tile round, M / KD waves share
-            // each group, PD partners a wave.
+            // A round of tiles covers KD decided groups, each shared by M / KD
+            // waves with PD partners a wave: KD = 1 in most kernels (every
+            // wave a P-partner slice of every group), KD = 8 in the eight-wave
+            // float kernels (every wave one group whole).
             {
                 constexpr int PD = kDecidedSlice<T, M, DA>;
                 constexpr int KD = PD / P;
@@ -1298,8 +1300,8 @@ __device__ __forceinline__ void sweep_chain(SweepShared<T, M, DA>& sh, const Cha
                     T sf = 0;
                     uint32_t nearm = 0;  // delayed acceptance: partners possibly within rc
                     if constexpr (UNIFORM_SIGMA || DA) {
-                        // a P-partner piece at a time (a loop, not unrolled:
-                        // the registers of the four-wave kernels' slices)
+                        // P partners at a time (a loop, not unrolled, so that a
+                        // round needs the registers of one P-partner slice)
 #pragma nounroll
                         for (int c = 0; c < KD; ++c)
 #pragma unroll
