@@ -92,7 +92,10 @@ typedef struct mc_options {
                                3 for float chains with per-ion diameters, for
                                float chains on eight waves and for the
                                delayed-acceptance kernel; to 2 for float
-                               chains with both                                */
+                               chains with both.  Automatic on eight waves: 1
+                               for a float chain whose workgroups serve at
+                               least four of its groups a sweep in the
+                               schedule planned at creation                    */
     int32_t waves;          /* waves per workgroup (4 or 8), 0 = automatic:
                                8 for float chains of at least 3 groups of 64
                                per compute unit in all (one chain: N >= 49089
